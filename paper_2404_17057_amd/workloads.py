@@ -1,0 +1,327 @@
+"""Seeded synthetic inputs: problem descriptions, particle clouds and obstacle
+geometry for the MPM workloads.
+
+This module is the only code shared by the GPU library's callers and the test
+oracle.  It builds *inputs* only -- domains, particle placement, initial
+states, obstacle masks and normals (the pre-processing stage of Sec. 3, step
+1 of the paper) -- and holds none of the time-stepping arithmetic.
+
+Workloads (all 2D unless stated, ideal gas gamma = 1.4):
+
+* ``sod``       -- quasi-1D shock tube (Sec. 4.1, Sod): left rho=1, p=1; right
+                   rho=0.125, p=0.1; diaphragm at x=0.5; walls everywhere.
+* ``cylinder``  -- supersonic flow past a circular cylinder (Sec. 4.1): inflow
+                   at x_lo, outflow (recycling) at x_hi, slip walls in y; far
+                   field rho=1.4, p=1 so that c=1 and Mach = |u|.
+* ``blast3d``   -- 3D spherical blast in the unit cube: rho=1, p=1e-5, and an
+                   inner sphere at p=1e3; walls everywhere.
+* ``quadrant``  -- 2x2-quadrant Riemann problem on the unit square, random
+                   per-quadrant states; walls everywhere.
+
+Particles sit on a regular s^d lattice in every fluid cell at offsets
+(j + 1/2)/s of the cell, each coordinate jittered by U(-0.05, 0.05) cells;
+the particle mass is rho(X) h^d / ppc.  Cells whose centre lies inside an
+obstacle get no particles.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+WALL, INFLOW, OUTFLOW = 0, 1, 2
+Q1, B2 = 1, 2
+AV_PAPER, AV_BOOK = 0, 1
+FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64 = 0, 1, 2, 3
+
+DEFAULT_SEED = 17057
+
+
+@dataclasses.dataclass
+class Problem:
+    """One MPM problem: descriptor values, particle arrays and obstacle data."""
+
+    name: str
+    dim: int
+    n: Tuple[int, int, int]
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    faces: Tuple[Tuple[int, int], Tuple[int, int], Tuple[int, int]]
+    x: np.ndarray            # (dim, N) float64
+    v: np.ndarray            # (dim, N) float64
+    mass: np.ndarray         # (N,)
+    rho: np.ndarray          # (N,)
+    eint: np.ndarray         # (N,) specific internal energy
+    ids: np.ndarray          # (N,) uint32, a permutation of 0..N-1
+    shape: int = B2
+    av_form: int = AV_PAPER
+    gamma: float = 1.4
+    c0: float = 1.0
+    c1: float = 1.0
+    cfl: float = 0.3
+    inflow_rho: float = 0.0
+    inflow_p: float = 0.0
+    inflow_u: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    recycle_mass: float = 0.0
+    seed: int = DEFAULT_SEED
+    t_end: float = 0.0
+    steps: int = 0                       # nominal step count of the workload
+    gradv: Optional[np.ndarray] = None   # (dim*dim, N) or None for zero
+    cell_mask: Optional[np.ndarray] = None   # uint8 over cells, x fastest
+    node_normal: Optional[np.ndarray] = None  # (dim, nodes) float64, x fastest
+
+    @property
+    def n_particles(self) -> int:
+        return int(self.mass.shape[0])
+
+    @property
+    def h(self) -> float:
+        return (self.hi[0] - self.lo[0]) / self.n[0]
+
+    def node_counts(self) -> Tuple[int, int, int]:
+        return node_counts(self.n, self.dim, self.shape)
+
+    def permuted(self, seed: int) -> "Problem":
+        """The same particle cloud handed over in a random order."""
+        perm = np.random.default_rng(seed).permutation(self.n_particles)
+        kw = dataclasses.asdict(self)
+        kw.update(x=self.x[:, perm].copy(), v=self.v[:, perm].copy(),
+                  mass=self.mass[perm].copy(), rho=self.rho[perm].copy(),
+                  eint=self.eint[perm].copy(), ids=self.ids[perm].copy(),
+                  gradv=None if self.gradv is None else self.gradv[:, perm].copy())
+        return Problem(**kw)
+
+
+# ---------------------------------------------------------------- geometry --
+
+def _lattice(n, lo, h, dim, per_axis, jitter, rng, cell_ok=None):
+    """Particle positions on the jittered lattice; returns (dim, N) and the
+    flat cell index of each particle."""
+    s = per_axis
+    off1 = (np.arange(s) + 0.5) / s
+    grids = np.meshgrid(*([off1] * dim), indexing="ij")
+    offs = np.stack([g.ravel() for g in reversed(grids)], axis=0)  # x fastest
+    ncell = int(np.prod(n[:dim]))
+    cells = np.arange(ncell, dtype=np.int64)
+    if cell_ok is not None:
+        cells = cells[cell_ok.ravel() != 0]
+    ci = []
+    rem = cells.copy()
+    for a in range(dim):
+        ci.append(rem % n[a])
+        rem //= n[a]
+    ci = np.stack(ci, axis=0)                                    # (dim, ncell')
+    nper = offs.shape[1]
+    pos = (ci[:, :, None] + offs[:, None, :]).reshape(dim, -1)   # cell units
+    pos = pos + rng.uniform(-jitter, jitter, size=pos.shape)
+    x = np.empty_like(pos)
+    for a in range(dim):
+        x[a] = lo[a] + pos[a] * h
+    cell_of = np.repeat(cells, nper)
+    return x, cell_of
+
+
+def node_counts(n, dim, shape):
+    """Nodes per axis: Q1 has the n+1 cell vertices; B2 (quadratic B-splines on
+    the clamped knot vector of the cell faces) has n+2 basis functions."""
+    extra = 2 if shape == B2 else 1
+    return tuple(n[a] + extra if a < dim else 1 for a in range(3))
+
+
+def node_axis(n_a, shape):
+    """Node coordinates along one axis in cell units: Q1 vertices 0..n; B2
+    Greville points 0, 1/2, 3/2, ..., n-1/2, n."""
+    if shape == B2:
+        return np.concatenate([[0.0], np.arange(n_a) + 0.5, [float(n_a)]])
+    return np.arange(n_a + 1, dtype=np.float64)
+
+
+def _node_positions(n, lo, h, dim, shape):
+    axes = [lo[a] + node_axis(n[a], shape) * h for a in range(dim)]
+    mesh = np.meshgrid(*reversed(axes), indexing="ij")
+    return [m.ravel() for m in reversed(mesh)]
+
+
+def circle_obstacle(n, lo, h, dim, shape, center, radius):
+    """Cell mask (cell centre inside the circle/sphere) and outward unit
+    normals (x_i - c)/|x_i - c| on every node (0 at the centre)."""
+    ncell = [n[a] for a in range(dim)]
+    cax = [lo[a] + (np.arange(ncell[a]) + 0.5) * h for a in range(dim)]
+    mesh = np.meshgrid(*reversed(cax), indexing="ij")
+    cc = [m.ravel() for m in reversed(mesh)]
+    r2 = sum((cc[a] - center[a]) ** 2 for a in range(dim))
+    mask = (r2 < radius * radius).astype(np.uint8)
+    nodes = _node_positions(n, lo, h, dim, shape)
+    d = np.stack([nodes[a] - center[a] for a in range(dim)], axis=0)
+    r = np.sqrt((d * d).sum(axis=0))
+    normal = np.where(r > 1e-12, d / np.where(r > 1e-12, r, 1.0), 0.0)
+    return mask, normal
+
+
+def _pad3(t, fill):
+    t = tuple(t)
+    return t + (fill,) * (3 - len(t))
+
+
+# ---------------------------------------------------------------- workloads --
+
+def sod(nx=256, ny=8, per_axis=2, jitter=0.05, seed=DEFAULT_SEED, shape=B2,
+        av_form=AV_PAPER, c0=1.0, c1=1.0, t_end=0.2, cfl=0.3) -> Problem:
+    """Quasi-1D Sod tube on [0,1] x [0, ny/nx] (square cells), walls."""
+    h = 1.0 / nx
+    n = (nx, ny, 1)
+    lo = (0.0, 0.0, 0.0)
+    hi = (1.0, ny * h, 0.0)
+    rng = np.random.default_rng(seed)
+    x, _ = _lattice(n, lo, h, 2, per_axis, jitter, rng)
+    left = x[0] < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    gamma = 1.4
+    N = x.shape[1]
+    ppc = per_axis ** 2
+    return Problem(
+        name=f"sod_{nx}x{ny}", dim=2, n=n, lo=lo, hi=hi,
+        faces=((WALL, WALL), (WALL, WALL), (WALL, WALL)),
+        x=x, v=np.zeros((2, N)), mass=rho * h * h / ppc, rho=rho,
+        eint=p / ((gamma - 1.0) * rho), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, c0=c0, c1=c1, cfl=cfl,
+        seed=seed, t_end=t_end, steps=0)
+
+
+def cylinder(nx=1024, ny=512, per_axis=2, mach=3.0, jitter=0.05, seed=DEFAULT_SEED,
+             shape=B2, av_form=AV_PAPER, lx=1.0, center=(0.3, 0.25), radius=0.05,
+             steps=2000, cfl=0.3) -> Problem:
+    """Mach `mach` flow past a cylinder on [0,lx] x [0, lx*ny/nx]."""
+    h = lx / nx
+    n = (nx, ny, 1)
+    lo = (0.0, 0.0, 0.0)
+    hi = (lx, ny * h, 0.0)
+    rho0, p0, gamma = 1.4, 1.0, 1.4
+    mask, normal = circle_obstacle(n, lo, h, 2, shape, center, radius)
+    rng = np.random.default_rng(seed)
+    ok = (1 - mask).reshape(ny, nx)
+    x, _ = _lattice(n, lo, h, 2, per_axis, jitter, rng, cell_ok=ok)
+    N = x.shape[1]
+    ppc = per_axis ** 2
+    m0 = rho0 * h * h / ppc
+    v = np.zeros((2, N))
+    v[0] = mach
+    return Problem(
+        name=f"cylinder_{nx}x{ny}_ppc{ppc}", dim=2, n=n, lo=lo, hi=hi,
+        faces=((INFLOW, OUTFLOW), (WALL, WALL), (WALL, WALL)),
+        x=x, v=v, mass=np.full(N, m0), rho=np.full(N, rho0),
+        eint=np.full(N, p0 / ((gamma - 1.0) * rho0)), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
+        inflow_rho=rho0, inflow_p=p0, inflow_u=(mach, 0.0, 0.0), recycle_mass=m0,
+        seed=seed, t_end=0.0, steps=steps, cell_mask=mask, node_normal=normal)
+
+
+def blast3d(n=256, per_axis=2, jitter=0.05, seed=DEFAULT_SEED, shape=B2,
+            av_form=AV_PAPER, radius=0.05, p_in=1e3, p_out=1e-5, steps=100,
+            cfl=0.3) -> Problem:
+    """Spherical blast in the unit cube, walls on all six faces."""
+    h = 1.0 / n
+    nn = (n, n, n)
+    lo = (0.0, 0.0, 0.0)
+    hi = (1.0, 1.0, 1.0)
+    gamma = 1.4
+    rng = np.random.default_rng(seed)
+    x, _ = _lattice(nn, lo, h, 3, per_axis, jitter, rng)
+    r2 = ((x - 0.5) ** 2).sum(axis=0)
+    p = np.where(r2 < radius * radius, p_in, p_out)
+    N = x.shape[1]
+    ppc = per_axis ** 3
+    rho = np.ones(N)
+    return Problem(
+        name=f"blast3d_{n}", dim=3, n=nn, lo=lo, hi=hi,
+        faces=((WALL, WALL), (WALL, WALL), (WALL, WALL)),
+        x=x, v=np.zeros((3, N)), mass=rho * h ** 3 / ppc, rho=rho,
+        eint=p / ((gamma - 1.0) * rho), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
+        seed=seed, t_end=0.0, steps=steps)
+
+
+def quadrant(n=256, per_axis=2, jitter=0.05, seed=DEFAULT_SEED, shape=B2,
+             av_form=AV_PAPER, steps=200, cfl=0.3) -> Problem:
+    """2x2-quadrant Riemann problem on the unit square; per-quadrant rho, p in
+    U[0.1, 2] and velocity components in U(-0.7, 0.7) (|u| < 1)."""
+    h = 1.0 / n
+    nn = (n, n, 1)
+    lo = (0.0, 0.0, 0.0)
+    hi = (1.0, 1.0, 0.0)
+    gamma = 1.4
+    rng = np.random.default_rng(seed)
+    q_rho = rng.uniform(0.1, 2.0, 4)
+    q_p = rng.uniform(0.1, 2.0, 4)
+    q_u = rng.uniform(-0.7, 0.7, (4, 2))
+    x, _ = _lattice(nn, lo, h, 2, per_axis, jitter, rng)
+    q = (x[0] >= 0.5).astype(int) + 2 * (x[1] >= 0.5).astype(int)
+    N = x.shape[1]
+    ppc = per_axis ** 2
+    rho = q_rho[q]
+    return Problem(
+        name=f"quadrant_{n}", dim=2, n=nn, lo=lo, hi=hi,
+        faces=((WALL, WALL), (WALL, WALL), (WALL, WALL)),
+        x=x, v=q_u[q].T.copy(), mass=rho * h * h / ppc, rho=rho,
+        eint=q_p[q] / ((gamma - 1.0) * rho), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
+        seed=seed, t_end=0.0, steps=steps)
+
+
+def uniform_box(dim=2, n=16, per_axis=2, rho=1.0, p=1.0, u=(0.0, 0.0, 0.0),
+                jitter=0.05, seed=DEFAULT_SEED, shape=B2, faces=None, steps=1,
+                cfl=0.3) -> Problem:
+    """A uniform state in a box; used by invariance checks."""
+    h = 1.0 / n
+    nn = _pad3((n,) * dim, 1)
+    lo = (0.0, 0.0, 0.0)
+    hi = _pad3((1.0,) * dim, 0.0)
+    gamma = 1.4
+    rng = np.random.default_rng(seed)
+    x, _ = _lattice(nn, lo, h, dim, per_axis, jitter, rng)
+    N = x.shape[1]
+    ppc = per_axis ** dim
+    v = np.zeros((dim, N))
+    for a in range(dim):
+        v[a] = u[a]
+    if faces is None:
+        faces = ((WALL, WALL),) * 3
+    return Problem(
+        name=f"uniform{dim}d_{n}", dim=dim, n=nn, lo=lo, hi=hi, faces=faces,
+        x=x, v=v, mass=np.full(N, rho * h ** dim / ppc), rho=np.full(N, rho),
+        eint=np.full(N, p / ((gamma - 1.0) * rho)), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, gamma=gamma, cfl=cfl, seed=seed, steps=steps)
+
+
+def random_blob(dim=2, n=12, count=300, seed=DEFAULT_SEED, shape=B2, margin=3,
+                faces=None) -> Problem:
+    """Particles with random positions, masses and states kept `margin` cells
+    away from every face; used by conservation checks."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = _pad3((n,) * dim, 1)
+    hi = _pad3((1.0,) * dim, 0.0)
+    x = rng.uniform(margin * h, 1.0 - margin * h, size=(dim, count))
+    rho = rng.uniform(0.5, 2.0, count)
+    p = rng.uniform(0.5, 2.0, count)
+    gamma = 1.4
+    if faces is None:
+        faces = ((WALL, WALL),) * 3
+    return Problem(
+        name=f"blob{dim}d", dim=dim, n=nn, lo=(0.0, 0.0, 0.0), hi=hi, faces=faces,
+        x=x, v=rng.uniform(-0.3, 0.3, size=(dim, count)),
+        mass=rng.uniform(0.5, 1.5, count) * h ** dim / 4, rho=rho,
+        eint=p / ((gamma - 1.0) * rho), ids=np.arange(count, dtype=np.uint32),
+        shape=shape, gamma=gamma, seed=seed, steps=1,
+        gradv=rng.uniform(-0.5, 0.5, size=(dim * dim, count)))
+
+
+WORKLOADS = {
+    "sod": sod,
+    "cylinder": cylinder,
+    "blast3d": blast3d,
+    "quadrant": quadrant,
+}

@@ -1,0 +1,427 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a shifted node index, a transposed gradient) fails at least one of
+them.  No value here comes from the GPU library.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact_riemann as R
+from oracle import oracle as O
+from paper_2404_17057_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+# ------------------------------------------------------------------ basis --
+
+def _greville(n, shape):
+    return W.node_axis(n, shape)
+
+
+@pytest.mark.parametrize("shape", [W.Q1, W.B2])
+@pytest.mark.parametrize("n", [2, 3, 7])
+def test_basis_partition_of_unity_and_linear_reproduction(shape, n):
+    """sum_j B_j = 1, sum_j B_j' = 0 and sum_j xi_j B_j(s) = s (Marsden's
+    identity with the Greville abscissae xi_j; vertices for Q1).  A node index
+    shifted by one breaks the first moment by a whole cell."""
+    xi = _greville(n, shape)
+    rng = np.random.default_rng(0)
+    pts = np.concatenate([rng.uniform(0, n, 400), np.arange(n) + 0.0, [n - 1e-12]])
+    for s in pts:
+        first, w, dw = O.basis_1d(shape, n, float(s))
+        assert abs(w.sum() - 1.0) < 1e-14
+        assert abs(dw.sum()) < 1e-13
+        assert abs((w * xi[first:first + len(w)]).sum() - s) < 1e-13
+        assert abs((dw * xi[first:first + len(w)]).sum() - 1.0) < 1e-13
+        assert (w >= -1e-15).all()
+
+
+def test_b2_interior_is_the_uniform_quadratic_bspline():
+    """Away from the faces the clamped basis equals the cardinal quadratic
+    B-spline, i.e. the box function convolved with itself twice (computed here
+    by numerical convolution, independently of the recursion)."""
+    n = 9
+    t = np.linspace(-2, 2, 40001)
+    dt = t[1] - t[0]
+    box = ((t >= -0.5) & (t < 0.5)).astype(float)
+    hat = np.convolve(box, box, mode="same") * dt
+    quad = np.convolve(hat, box, mode="same") * dt
+    for s in [3.1, 4.5, 5.77, 2.0, 6.999]:
+        first, w, _ = O.basis_1d(W.B2, n, s)
+        for j in range(3):
+            centre = first + j - 0.5            # Greville point of B_{first+j}
+            ref = np.interp(s - centre, t, quad)
+            assert abs(w[j] - ref) < 2e-4
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_b2_is_c1_and_derivative_matches_finite_differences(n):
+    xi = np.linspace(1e-6, n - 1e-6, 3001)
+    vals = np.zeros((n + 2, xi.size))
+    ders = np.zeros((n + 2, xi.size))
+    for k, s in enumerate(xi):
+        first, w, dw = O.basis_1d(W.B2, n, float(s))
+        vals[first:first + 3, k] = w
+        ders[first:first + 3, k] = dw
+    fd = np.gradient(vals, xi, axis=1)
+    assert np.abs(fd - ders).max() < 5e-3          # derivative formula
+    ds = xi[1] - xi[0]
+    # |B'| <= 2 and |B''| <= 3 everywhere: a jump would exceed these steps
+    assert np.abs(np.diff(vals, axis=1)).max() < 2.01 * ds   # continuous value
+    assert np.abs(np.diff(ders, axis=1)).max() < 3.01 * ds   # continuous slope (C1)
+    # only the first function is non-zero on the low face, the last on the high face
+    first, w, _ = O.basis_1d(W.B2, n, 0.0)
+    assert first == 0 and abs(w[0] - 1.0) < 1e-15 and abs(w[1:]).max() < 1e-15
+
+
+# ------------------------------------------------------ constitutive laws --
+
+def test_artificial_viscosity_closed_forms():
+    g, h = 1.4, 0.01
+    for form in (W.AV_PAPER, W.AV_BOOK):
+        assert O.artificial_viscosity(form, 1, 1, g, h, 1.3, 0.7, 0.0) == 0.0
+        assert O.artificial_viscosity(form, 1, 1, g, h, 1.3, 0.7, 2.5) == 0.0
+    rho, p, D = 2.0, 3.0, -5.0
+    c = np.sqrt(g * p / rho)
+    paper = 1 * (rho * h * D) ** 2 - 1 * h * c * D
+    book = 1 * rho * (h * D) ** 2 - 1 * rho * h * c * D
+    assert np.isclose(O.artificial_viscosity(W.AV_PAPER, 1, 1, g, h, rho, p, D), paper, rtol=1e-15)
+    assert np.isclose(O.artificial_viscosity(W.AV_BOOK, 1, 1, g, h, rho, p, D), book, rtol=1e-15)
+    # the two terms separately (Sec. 4.2 switches each one off)
+    assert np.isclose(O.artificial_viscosity(W.AV_PAPER, 0, 1, g, h, rho, p, D), -h * c * D, rtol=1e-15)
+    assert np.isclose(O.artificial_viscosity(W.AV_PAPER, 1, 0, g, h, rho, p, D), (rho * h * D) ** 2, rtol=1e-15)
+
+
+def test_obstacle_projection():
+    n = np.array([0.6, 0.8])
+    inward = np.array([-1.0, -2.0])       # u.n < 0: the normal part is removed
+    out = O.obstacle_project(n, inward)
+    assert abs(out @ n) < 1e-15
+    assert np.allclose(out - inward, -(inward @ n) * n, atol=1e-15)
+    assert np.allclose(O.obstacle_project(n, out), out, atol=1e-15)     # idempotent
+    outward = np.array([1.0, 0.5])
+    assert np.array_equal(O.obstacle_project(n, outward), outward)      # untouched
+    tangent = np.array([0.8, -0.6])
+    assert np.allclose(O.obstacle_project(n, tangent), tangent, atol=1e-15)
+
+
+def test_splitmix64_published_sequence():
+    ref = json.load(open(os.path.join(GOLDEN, "splitmix64_state0.json")))
+    inc = int(ref["increment_hex"], 16)
+    state = 0
+    for h in ref["outputs_hex"]:
+        assert O.splitmix64(state) == int(h, 16)
+        state = (state + inc) & 0xFFFFFFFFFFFFFFFF
+
+
+# ----------------------------------------------------------------- G2PD --
+
+@pytest.mark.parametrize("shape", [W.Q1, W.B2])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_of_linear_field_is_exact(shape, dim):
+    """A nodal field sampled from v(x) = A x + b has G = A exactly (rows =
+    velocity component, columns = derivative direction); A is not symmetric,
+    so a transposed gradient fails."""
+    pb = W.uniform_box(dim=dim, n=6, shape=shape)
+    nodes = pb.node_counts()
+    ax = [pb.lo[a] + W.node_axis(pb.n[a], shape) * pb.h for a in range(dim)]
+    mesh = np.meshgrid(*reversed(ax), indexing="ij")
+    pos = np.stack([m.ravel() for m in reversed(mesh)])
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(dim, dim))
+    b = rng.normal(size=dim)
+    u = A @ pos + b[:, None]
+    for pt in rng.uniform(0.0, 1.0, size=(20, dim)):
+        G = O.nodal_gradient(pb, u, pt)
+        assert np.abs(G - A).max() < 1e-11
+    assert int(np.prod(nodes)) == pos.shape[1]
+
+
+# --------------------------------------------------------- time stepping --
+
+def test_single_particle_p2g_moments():
+    """One particle: nodal mass sums to M, its first moment about the node
+    positions is M X (linear reproduction), nodal momentum is M V weights."""
+    pb = W.random_blob(dim=2, n=8, count=1, margin=2)
+    o = O.Oracle(pb)
+    o.step(1)
+    m = o.grid(O.G_M)
+    p = o.grid(O.G_P)
+    nodes = pb.node_counts()
+    xi = pb.lo[0] + W.node_axis(pb.n[0], pb.shape) * pb.h
+    yi = pb.lo[1] + W.node_axis(pb.n[1], pb.shape) * pb.h
+    X = np.repeat(yi, nodes[0]) * 0 + np.tile(xi, nodes[1])
+    Y = np.repeat(yi, nodes[0])
+    M = pb.mass[0]
+    assert np.isclose(m.sum(), M, rtol=1e-14)
+    assert np.isclose((m * X).sum(), M * pb.x[0, 0], rtol=1e-13)
+    assert np.isclose((m * Y).sum(), M * pb.x[1, 0], rtol=1e-13)
+    assert np.allclose(p[0], m * pb.v[0, 0], rtol=1e-13, atol=0)
+    assert (m > 0).sum() == 9
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_conservation_on_interior_blob(dim):
+    """No boundary node is touched: mass, momentum sums are exact; the
+    internal forces sum to zero; the G2P/P2G momentum identities hold and the
+    particle momentum is conserved by the step."""
+    pb = W.random_blob(dim=dim, n=10, count=400 if dim == 2 else 300, margin=3)
+    o = O.Oracle(pb)
+    o.set_dt(1e-3)
+    o.step(1)
+    m = o.grid(O.G_M)
+    p = o.grid(O.G_P)
+    f = o.grid(O.G_F)
+    pu = o.grid(O.G_PUPD)
+    M = pb.mass
+    assert np.isclose(m.sum(), M.sum(), rtol=1e-13)
+    assert np.allclose(p.sum(axis=1), (M * pb.v).sum(axis=1), rtol=1e-12, atol=1e-16)
+    assert np.abs(f.sum(axis=1)).max() < 1e-12 * np.abs(f).max() * f.shape[1]
+    assert np.abs(f).max() > 0
+    vbar = o.particles(O.F_VBAR)
+    assert np.allclose((M * vbar).sum(axis=1), pu.sum(axis=1), rtol=1e-11, atol=1e-15)
+    V1 = o.particles(O.F_V)
+    assert np.allclose((M * V1).sum(axis=1), (M * pb.v).sum(axis=1), rtol=1e-11, atol=1e-15)
+    st = o.status()
+    assert st["conserved"][0] == pytest.approx(M.sum(), rel=1e-14)
+
+
+def test_move_uses_updated_grid_momentum():
+    """From rest the grid momentum after the update is dt f, so the G2P
+    velocity used for the move (Vbar, from (mv)' = mv + dt f) equals the new
+    particle velocity V' = dt A; using mv before the update gives Vbar = 0."""
+    pb = W.random_blob(dim=2, n=10, count=300, margin=3)
+    pb.v[:] = 0.0
+    o = O.Oracle(pb)
+    o.set_dt(1e-3)
+    o.step(1)
+    vbar = o.particles(O.F_VBAR)
+    v1 = o.particles(O.F_V)
+    assert np.abs(v1).max() > 1e-4
+    assert np.abs(vbar - v1).max() < 1e-14 * np.abs(v1).max() * 10
+
+
+def test_force_sign_pushes_away_from_pressure():
+    """A single pressurised particle pushes the nodes on its right to the
+    right and those on its left to the left (force = +(P+Q) Vol grad phi)."""
+    pb = W.random_blob(dim=2, n=8, count=1, margin=2)
+    o = O.Oracle(pb)
+    o.step(1)
+    f = o.grid(O.G_F)
+    nodes = pb.node_counts()
+    xi = pb.lo[0] + W.node_axis(pb.n[0], pb.shape) * pb.h
+    X = np.tile(xi, nodes[1])
+    touched = np.abs(f[0]) > 0
+    right = touched & (X > pb.x[0, 0])
+    left = touched & (X < pb.x[0, 0])
+    assert (f[0][right] > 0).all() and (f[0][left] < 0).all()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_uniform_lattice_at_rest_stays_at_rest(dim):
+    """Regular lattice, uniform state, walls: every interior force vanishes
+    (the two-point-per-cell rule integrates the basis derivatives exactly), so
+    the gas stays at rest; dt is the closed form CFL h / c."""
+    pb = W.uniform_box(dim=dim, n=6 if dim == 3 else 10, jitter=0.0, rho=1.3, p=0.9)
+    o = O.Oracle(pb)
+    c = np.sqrt(1.4 * 0.9 / 1.3)
+    assert o.status()["dt_next"] == pytest.approx(0.3 * pb.h / c, rel=1e-14)
+    o.step(10)
+    assert np.abs(o.particles(O.F_V)).max() < 1e-12
+    assert np.abs(o.particles(O.F_RHO) - 1.3).max() < 1e-12
+
+
+def test_uniform_translation_is_reproduced():
+    """A pressureless gas in uniform motion with no face constraint: G2P
+    returns the velocity, the velocity gradient vanishes, and every particle
+    moves by dt V (P2G followed by G2P reproduces a constant field)."""
+    pb = W.uniform_box(dim=2, n=12, jitter=0.05, u=(0.2, -0.1, 0.0), p=0.0)
+    pb.faces = ((W.OUTFLOW, W.OUTFLOW), (W.OUTFLOW, W.OUTFLOW), (W.WALL, W.WALL))
+    o = O.Oracle(pb)
+    o.set_dt(1e-3)
+    o.step(1)
+    vbar = o.particles(O.F_VBAR)
+    assert np.abs(vbar[0] - 0.2).max() < 1e-14
+    assert np.abs(vbar[1] + 0.1).max() < 1e-14
+    assert np.abs(o.particles(O.F_G)).max() < 1e-12
+    assert np.abs(o.particles(O.F_X) - (pb.x + 1e-3 * pb.v)).max() < 1e-15
+
+
+def test_boundary_conditions_in_a_step():
+    """Walls null the normal momentum of their boundary nodes; inflow nodes
+    carry m u_in and no force; obstacle nodes keep no inward momentum."""
+    pb = W.cylinder(nx=64, ny=32, steps=3)
+    o = O.Oracle(pb)
+    o.step(3)
+    nodes = pb.node_counts()
+    m = o.grid(O.G_M).reshape(nodes[1], nodes[0])
+    pu = o.grid(O.G_PUPD).reshape(2, nodes[1], nodes[0])
+    p = o.grid(O.G_P).reshape(2, nodes[1], nodes[0])
+    f = o.grid(O.G_F).reshape(2, nodes[1], nodes[0])
+    fbc = o.grid(O.G_FBC).reshape(2, nodes[1], nodes[0])
+    p2 = o.grid(O.G_P2).reshape(2, nodes[1], nodes[0])
+    # y walls: boundary rows
+    assert np.abs(pu[1][0]).max() == 0 and np.abs(pu[1][-1]).max() == 0
+    assert np.abs(p2[1][0]).max() == 0 and np.abs(p2[1][-1]).max() == 0
+    assert np.abs(fbc[1][0]).max() == 0
+    # inflow column x = 0: momentum = m u_in (rows 1..-2; corners are walls too)
+    assert np.allclose(pu[0][1:-1, 0], 3.0 * m[1:-1, 0], rtol=1e-14)
+    assert np.abs(fbc[:, :, 0]).max() == 0
+    # obstacle nodes: no inward normal momentum after the conditions
+    nrm = pb.node_normal.reshape(2, nodes[1], nodes[0])
+    mask = pb.cell_mask.reshape(pb.n[1], pb.n[0])
+    jy, jx = np.meshgrid(np.arange(nodes[1]), np.arange(nodes[0]), indexing="ij")
+    cx = np.clip(jx - 1, 0, pb.n[0] - 1)
+    cy = np.clip(jy - 1, 0, pb.n[1] - 1)
+    obst = mask[cy, cx] != 0
+    assert obst.sum() > 0
+    un2 = (p2 * nrm).sum(axis=0)
+    assert (un2[obst] >= -1e-15).all()
+    # the conditions changed something: the raw map had inward momentum there
+    assert ((p * nrm).sum(axis=0)[obst] < 0).any()
+
+
+def test_total_mass_constant_with_recycling():
+    pb = W.cylinder(nx=32, ny=16, steps=60)
+    o = O.Oracle(pb)
+    M0 = pb.mass.sum()
+    o.step(60)
+    x = o.particles(O.F_X)
+    assert np.array_equal(o.particles(O.F_M), pb.mass)   # masses are never altered
+    assert o.status()["conserved"][0] == pytest.approx(M0, rel=1e-14)
+    assert (x[0] >= 0).all() and (x[0] < 1).all()
+    assert o.status()["wall_escapes"] == 0
+
+
+def test_recycled_particle_position_follows_the_hash():
+    """A particle about to leave through the outflow re-enters at
+    x - L with y drawn from splitmix64(seed ^ step<<32 ^ id)."""
+    pb = W.cylinder(nx=32, ny=16, steps=1)
+    k = int(np.argmax(pb.x[0]))            # right-most particle
+    pb.x[0, k] = 1.0 - 1e-6
+    o = O.Oracle(pb)
+    dt = o.status()["dt_next"]
+    o.step(1)
+    x = o.particles(O.F_X)
+    word = (pb.seed ^ (0 << 32) ^ k) & 0xFFFFFFFFFFFFFFFF
+    u = (O.splitmix64(word) >> 11) * 2.0 ** -53
+    assert x[1, k] == pytest.approx(pb.lo[1] + (pb.hi[1] - pb.lo[1]) * u, rel=0, abs=1e-15)
+    assert 0 <= x[0, k] < dt * 4
+    assert o.particles(O.F_RHO)[k] == 1.4
+    assert np.array_equal(o.particles(O.F_V)[:, k], [3.0, 0.0])
+
+
+# ------------------------------------------------------------------- Sod --
+
+def test_exact_riemann_solver_against_tabulated_star_state():
+    ref = json.load(open(os.path.join(GOLDEN, "sod_star_state.json")))
+    ps, us = R.star_state(ref["left"], ref["right"], ref["gamma"])
+    rho, _, _ = R.sample(ref["left"], ref["right"], [us - 1e-9, us + 1e-9], ref["gamma"])
+    tol = 0.5 * 10 ** -ref["digits"]
+    assert abs(ps - ref["p_star"]) <= tol
+    assert abs(us - ref["u_star"]) <= tol
+    assert abs(rho[0] - ref["rho_star_left"]) <= tol
+    assert abs(rho[1] - ref["rho_star_right"]) <= tol
+
+
+def test_exact_riemann_solver_jump_conditions():
+    """Rankine-Hugoniot across the shock and isentropy across the fan."""
+    g = 1.4
+    L, Rr = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    wp = R.wave_positions(L, Rr, 1.0, x0=0.0)
+    S = wp["shock"]
+    rho, u, p = R.sample(L, Rr, [S - 1e-9, S + 1e-9], g)
+    E = p / (g - 1) + 0.5 * rho * u * u
+    flux = lambda k: np.array([rho[k] * u[k], rho[k] * u[k] ** 2 + p[k], u[k] * (E[k] + p[k])])
+    cons = lambda k: np.array([rho[k], rho[k] * u[k], E[k]])
+    assert np.allclose(flux(0) - flux(1), S * (cons(0) - cons(1)), atol=1e-10)
+    xs = np.linspace(wp["head"], wp["tail"], 7)
+    rho, u, p = R.sample(L, Rr, xs, g)
+    assert np.allclose(p / rho ** g, 1.0, atol=1e-12)
+    c = np.sqrt(g * p / rho)
+    assert np.allclose(u + 2 * c / (g - 1), 2 * np.sqrt(g) / (g - 1), atol=1e-12)
+
+
+def _sod_l1(nx, jitter, av=W.AV_PAPER, c0=1.0, c1=1.0):
+    pb = W.sod(nx=nx, ny=max(2, nx // 32), jitter=jitter, av_form=av, c0=c0, c1=c1)
+    o = O.Oracle(pb)
+    assert o.step(0) == 0
+    st = o.status()
+    assert st["t"] == 0.2
+    x = o.particles(O.F_X)
+    rho = o.particles(O.F_RHO)
+    vol = o.particles(O.F_VOL)
+    ex, _, _ = R.sample((1, 0, 1), (0.125, 0, 0.1), (x[0] - 0.5) / st["t"])
+    return float((vol * np.abs(rho - ex)).sum() / vol.sum()), o, pb
+
+
+def test_sod_converges_to_exact_solution_under_refinement():
+    """Regular lattice (the paper places Sod particles regularly): the
+    volume-weighted L1 density error against the exact solution shrinks on
+    each refinement 64x2 -> 128x4 -> 256x8."""
+    errs = [_sod_l1(nx, 0.0)[0] for nx in (64, 128, 256)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.012
+    assert errs[2] < 0.5 * errs[0]
+
+
+def test_sod_energy_and_mass_conservation():
+    """Walls do no work: total energy sum M (e + |v|^2/2) is conserved by the
+    scheme to the time-integration error; dropping the artificial pressure
+    from the energy equation, or flipping its sign, breaks this by far more."""
+    _, o, pb = _sod_l1(128, 0.05)
+    e0 = (pb.mass * pb.eint).sum()
+    c = o.status()["conserved"]
+    assert c[0] == pytest.approx(pb.mass.sum(), rel=1e-15)
+    assert abs(c[4] + c[5] - e0) < 2e-3 * e0
+    assert c[5] > 0.02 * e0           # a real flow developed
+
+
+def test_artificial_viscosity_damps_post_shock_oscillations():
+    """Sec. 4.2: without artificial viscosity the post-shock plateau rings;
+    with c0 = c1 = 1 it is smoother (regular lattice, 128x4)."""
+    def plateau_std(c0, c1):
+        _, o, _ = _sod_l1(128, 0.0, c0=c0, c1=c1)
+        x = o.particles(O.F_X)
+        v = o.particles(O.F_V)
+        sel = (x[0] > 0.72) & (x[0] < 0.78)
+        return v[0][sel].std()
+    assert plateau_std(0.0, 0.0) > 1.5 * plateau_std(1.0, 1.0)
+
+
+def test_nonphysical_compression_is_reported():
+    """J = 1 + dt div v <= 0 is an error: two streams collide head on with a
+    time step far beyond the CFL bound."""
+    pb = W.uniform_box(dim=2, n=8, jitter=0.0)
+    pb.v[0] = np.where(pb.x[0] < 0.5, 5.0, -5.0)
+    o = O.Oracle(pb)
+    o.set_dt(0.5)
+    assert o.step(1) == O.OracleError(-4, "").code
+    assert o.step(1) == -7
+
+
+def test_create_rejects_bad_input():
+    pb = W.uniform_box(dim=2, n=4)
+    bad = W.Problem(**{**pb.__dict__})
+    bad.ids = np.zeros_like(pb.ids)
+    with pytest.raises(O.OracleError):
+        O.Oracle(bad)
+    bad = W.Problem(**{**pb.__dict__})
+    bad.hi = (1.0, 0.5, 0.0)          # unequal cells
+    with pytest.raises(O.OracleError):
+        O.Oracle(bad)
+    bad = W.Problem(**{**pb.__dict__})
+    bad.x = pb.x.copy()
+    bad.x[0, 0] = 1.5                 # outside the box
+    with pytest.raises(O.OracleError):
+        O.Oracle(bad)
