@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the MPM hot path on one MI355X.
+
+Workload: Mach-3 flow past a cylinder (r = 0.05 at (0.3, 0.25)) in
+[0,1]x[0,0.5], 1024x512 cells, 2x2 jittered particles per fluid cell
+(2,064,184 particles), quadratic B-splines, CFL 0.3.  A step is one pass of
+the whole path: cell sort, P2G, boundary conditions and grid update, G2P and
+velocity update, P2G of the updated momentum, G2PD and particle update, move
+with outflow recycling, time step.  Inputs are resident in HBM before the
+timed region; the timed region is `--steps` steps (graph replays) bracketed
+by device synchronisation, timed with HIP events on the launch stream.
+
+Prints one JSON line: FP32 state with 64-bit fixed-point P2G (the headline
+value), the plain FP64 path beside it, the per-sweep times and the roofline
+of the dominant sweep, the FP64 oracle timed on the host cores on a bounded
+sample of the same workload, and the relative L1 density error of both GPU
+paths against the oracle after that sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (P2G+grid+G2P) FP32 vs FP64 plain at L1 err; p50/p99 serve"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
+    """Algorithmic bytes per launch of each sweep: every particle field and
+    grid word the sweep must read or write, counted once (no halo re-reads,
+    no atomic retries, no cache effects)."""
+    d = pb.dim
+    N = pb.n_particles
+    r, a = real_sz, acc_sz
+    nq = 1 + 2 * d
+    return {
+        "clear": nnodes * (nq + d) * a + ncells * 4,
+        "p2g": N * (3 * d + 3) * r + ncells * 4 + nnodes * nq * a,
+        "g2p_p2g": N * ((3 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
+        "scan_a": ncells * 4,
+        "scan_b": 0,
+        "scan_c": ncells * 8,
+        "update": N * ((3 * d + 3) * r + 12 + (2 * d + 3 + d * d) * r + 4 + 4) + nnodes * ((1 + 3 * d) * a + 1),
+        "finalize": 0,
+    }
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mpm_kernels.hip", "mpm_device.hpp", "mpm_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2404_17057_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, src_hash):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    valid only while the kernel source is the one the counters were taken
+    from."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        rec = data.get(workload, {}).get(kernel)
+        if rec and rec.get("source_hash") == src_hash:
+            return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def time_gpu(pb, precision, steps, warmup, profile_steps):
+    import torch
+    from paper_2404_17057_amd import mpm as G
+    sim = G.Simulation(pb, precision)
+    stream = torch.cuda.current_stream()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = sim.status()
+    if st["rc"] != 0:
+        raise RuntimeError(f"device error {st['rc']} during the timed steps")
+    prof = sim.profile(profile_steps) if profile_steps > 0 else {}
+    out = dict(ms_total=ms, ms_per_step=ms / steps, value=pb.n_particles * steps / (ms * 1e-3),
+               sweeps_ms=prof, nodes=sim.nnodes, counters=[int(c) for c in sim.counters()],
+               t=st["t"], step=st["step"])
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_sample_gpu(pb, precision, steps):
+    from paper_2404_17057_amd import mpm as G
+    sim = G.Simulation(pb, precision)
+    sim.step(steps)
+    rho = sim.field(G.F_RHO)
+    sim.close()
+    return rho
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="oracle steps timed on the host (bounded sample)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--nx", type=int, default=1024)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent problems would shard one per GPU with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2404_17057_amd import mpm as G
+    from paper_2404_17057_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    pb = W.cylinder(nx=args.nx, ny=args.nx // 2)
+    N = pb.n_particles
+    log(f"workload {pb.name}: {N} particles")
+
+    fix = time_gpu(pb, G.FP32_FIX64, args.steps, args.warmup, args.profile_steps)
+    log(f"fp32_fix64: {fix['ms_per_step']:.4f} ms/step, {fix['value']:.4e} particle-steps/s, sweeps {fix['sweeps_ms']}")
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = time_gpu(pb, G.FP64, args.steps, args.warmup, args.profile_steps)
+        log(f"fp64: {fp64['ms_per_step']:.4f} ms/step, {fp64['value']:.4e} particle-steps/s")
+
+    nnodes = fix["nodes"]
+    ntiles = ((pb.n[0] + 15) // 16) * ((pb.n[1] + 15) // 16)
+    ncells = ntiles * 256
+    bytes_fix = sweep_bytes(pb, nnodes, ncells, 4, 8)
+    sw = fix["sweeps_ms"]
+    dominant = max(sw, key=sw.get) if sw else "update"
+    dom_ms = sw.get(dominant, float("nan"))
+    achieved = bytes_fix[dominant] / (dom_ms * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = measured_traffic(dominant, pb.name, src_hash)
+    step_bytes = sum(bytes_fix.values())
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": dominant, "kernel_ms": round(dom_ms, 5),
+                "algorithmic_bytes_per_launch": int(bytes_fix[dominant]),
+                "step_algorithmic_bytes": int(step_bytes),
+                "step_achieved_GBps": round(step_bytes / (fix["ms_per_step"] * 1e-3) / 1e9, 1)}
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu and args.cpu_steps > 0:
+        from oracle import oracle as O
+        O.build(force=False)
+        t0 = time.perf_counter()
+        o = O.Oracle(pb)
+        t1 = time.perf_counter()
+        o.step(args.cpu_steps)
+        t2 = time.perf_counter()
+        cpu = {"value": round(N * args.cpu_steps / (t2 - t1), 1), "unit": "particle-steps/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"first {args.cpu_steps} steps of the same {pb.name} problem "
+                         f"({N} particles), sequential FP64 C, one host thread; setup {t1 - t0:.1f} s excluded"}
+        log(f"cpu oracle: {cpu['value']:.3e} particle-steps/s over {t2 - t1:.1f} s")
+        rho_o = o.particles(O.F_RHO)
+        l1 = lambda r: float(np.abs(r - rho_o).sum() / np.abs(rho_o).sum())
+        accuracy = {"steps": args.cpu_steps,
+                    "rel_l1_density_fp32_fix64": l1(run_sample_gpu(pb, G.FP32_FIX64, args.cpu_steps))}
+        if not args.no_fp64:
+            accuracy["rel_l1_density_fp64"] = l1(run_sample_gpu(pb, G.FP64, args.cpu_steps))
+        o.close()
+
+    line = {
+        "metric": METRIC,
+        "value": round(fix["value"], 1),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fix["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cylinder_mach3_{pb.n[0]}x{pb.n[1]}_ppc4", "particles": N,
+                   "precision": "fp32 state, int64 fixed-point P2G", "shape": "quadratic B-spline",
+                   "cfl": 0.3, "steps_run": fix["step"], "t_reached": round(fix["t"], 6)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64": None if fp64 is None else {"value": round(fp64["value"], 1),
+                                          "ms_per_step": round(fp64["ms_per_step"], 5),
+                                          "sweeps_ms": fp64["sweeps_ms"]},
+        "sweeps_ms": sw,
+        "accuracy_vs_oracle": accuracy,
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * mpm.h -- C ABI of the MI355X (gfx950) implementation of the per-step hot
+ * path of the compressible-gas Material Point Method of Baioni, Benacchio,
+ * Capone, de Falco, "Portable, massively parallel implementation of a
+ * Material Point Method for compressible flows" (arXiv 2404.17057).
+ *
+ * One time step (Sec. 3, steps (i)-(xii); Algorithm 1 "Time loop sketch"):
+ *   cell sort of the particles (step (xi), optional re-ordering, here every step)
+ *   P2G of mass and momentum, P2GD of the internal force (step (ii); eqs.
+ *     p2g_gen, p2gd_gen, mxa=f)
+ *   obstacle, wall and inflow conditions on momentum and force (step (iii);
+ *     eqs. normali1, normali2; wind-tunnel conditions of Sec. 4.1)
+ *   grid momentum update (step (iv))
+ *   G2P of velocity and acceleration, FLIP velocity update (step (v); eq. g2p_gen)
+ *   P2G of the updated momentum and its boundary conditions (steps (vi)-(vii))
+ *   G2PD velocity gradient, energy, density and pressure update (step (viii);
+ *     eq. g2pd_gen; ideal-gas state equation and artificial viscosity, eq. muart)
+ *   postponed move with the G2P velocity (step (ix)), outflow recycling (Sec. 4.1)
+ *   CFL time step from particle velocities and sound speed (step (xi); Sec. 2.2, CFL)
+ *
+ * Conventions
+ *   - Every call returns an int status (MPM_OK or a negative MPM_E_* code);
+ *     no exception crosses the ABI; out-parameters are untouched on error.
+ *   - Device memory: the caller owns one device workspace of at least
+ *     mpm_footprint() bytes per problem and keeps it alive until
+ *     mpm_destroy().  The library allocates no device memory on the stepping
+ *     path (mpm_read_grid and mpm_step_batch's graph cache excepted, see there).
+ *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the
+ *     default stream).  All work is enqueued on it; mpm_step and
+ *     mpm_step_batch return without waiting.
+ *   - The handle is owned by the library and is not thread-safe.
+ *   - Errors detected on the device (J = 1 + dt div v <= 0, non-finite
+ *     state, fixed-point overflow, a particle leaving through a wall) are
+ *     sticky: the problem stops advancing and the next mpm_status /
+ *     mpm_read_fields returns the code.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    MPM_OK = 0,
+    MPM_E_ARG = -1,          /* invalid argument or descriptor                 */
+    MPM_E_WORKSPACE = -2,    /* workspace missing, misaligned or too small     */
+    MPM_E_HIP = -3,          /* a HIP runtime call failed                      */
+    MPM_E_NONPHYSICAL = -4,  /* J <= 0 or a non-finite value on the device     */
+    MPM_E_OVERFLOW = -5,     /* fixed-point accumulator out of range           */
+    MPM_E_UNSUPPORTED = -6,  /* valid request this build does not implement    */
+    MPM_E_STATE = -7         /* operation not allowed in the handle's state    */
+};
+
+/* Basis functions (Sec. 2.2: Q1 bilinear/trilinear elements; quadratic
+ * B-splines on the clamped knot vector of the cell faces, the higher-order
+ * basis named in Sec. 5). */
+enum { MPM_Q1 = 1, MPM_B2 = 2 };
+
+/* Arithmetic of the particle state and of the P2G accumulation. */
+enum {
+    MPM_FP64 = 0,          /* FP64 state, FP64 atomic accumulation              */
+    MPM_FP32_ACC_F64 = 1,  /* FP32 state, FP64 atomic accumulation              */
+    MPM_FP32_ACC_F32 = 2,  /* FP32 state, FP32 atomic accumulation              */
+    MPM_FP32_FIX64 = 3     /* FP32 state, 64-bit fixed-point integer accumulation:
+                              sums are order-independent and bit-reproducible   */
+};
+
+/* Domain face types (Sec. 4.1, eq. bc). */
+enum { MPM_FACE_WALL = 0, MPM_FACE_INFLOW = 1, MPM_FACE_OUTFLOW = 2 };
+
+/* Artificial viscosity (Sec. 2.1, eq. muart): as printed,
+ * q = c0 (rho h D)^2 - c1 h sqrt(gamma p / rho) D, or the textbook form
+ * q = c0 rho (h D)^2 - c1 rho h c D; both only where D = div v < 0. */
+enum { MPM_AV_PAPER = 0, MPM_AV_BOOK = 1 };
+
+typedef struct {
+    int32_t dim;            /* 2 or 3                                              */
+    int32_t n[3];           /* cells per axis (>= 2; n[2] ignored in 2D)           */
+    double lo[3], hi[3];    /* domain box; cells must be square/cubic (equal h)     */
+    int32_t shape;          /* MPM_Q1 or MPM_B2                                     */
+    int32_t precision;      /* MPM_FP64 ... MPM_FP32_FIX64                          */
+    int32_t av_form;        /* MPM_AV_PAPER or MPM_AV_BOOK                          */
+    double gamma, c0, c1;   /* ideal gas ratio; artificial viscosity constants      */
+    double cfl;             /* dt = cfl * h / (max|v| + max c)                      */
+    int32_t face[3][2];     /* per axis: [low face, high face] type                 */
+    double inflow_rho, inflow_p, inflow_u[3]; /* state imposed at INFLOW faces and
+                                                 given to recycled particles       */
+    double recycle_mass;    /* mass of a recycled particle                          */
+    int64_t n_particles;
+    uint64_t seed;          /* key of the recycling hash                            */
+    double t_end;           /* > 0: the last step is shortened to land on t_end     */
+    double rho_ref, u_ref;  /* fixed-point references; 0 = derived from the initial
+                               state (max density; 4 max(|v| + c))                  */
+} mpm_desc;
+
+/* Host particle arrays, all of length n_particles, read only during
+ * mpm_init.  x, v: dim arrays; gradv: dim*dim arrays, row-major
+ * gradv[a*dim+b] = d v_a / d x_b, or all NULL for zero; id: a permutation of
+ * 0..n_particles-1 (results are returned in id order). */
+typedef struct {
+    const double *x[3];
+    const double *v[3];
+    const double *mass;
+    const double *rho;
+    const double *eint;     /* specific internal energy                             */
+    const double *gradv[9];
+    const uint32_t *id;
+} mpm_particles_host;
+
+/* Obstacle (Sec. 2.2, eqs. normali1/normali2, sdf), host arrays read only
+ * during mpm_init; pass NULL for none.  cell_mask: one byte per cell, x
+ * fastest (non-zero = obstacle cell).  node_normal: dim arrays over the
+ * node grid (mpm_grid_shape), x fastest, unit normals pointing out of the
+ * obstacle.  Obstacle nodes are the nodes whose position lies in a masked
+ * cell (Q1: cell vertices; B2: Greville points 0, 1/2, 3/2, ..., n-1/2, n). */
+typedef struct {
+    const uint8_t *cell_mask;
+    const double *node_normal[3];
+} mpm_obstacle_host;
+
+typedef struct mpm_handle mpm_handle;
+
+/* Device bytes one problem needs in its workspace.  Errors: MPM_E_ARG. */
+int mpm_footprint(const mpm_desc *desc, size_t *device_bytes);
+
+/* Build a problem in the caller's workspace (device pointer, 256-byte
+ * aligned, >= mpm_footprint bytes): copies the particles to the device
+ * (one host-to-device transfer, converted to the state precision), sets up
+ * boundary flags and normals, fixed-point quanta, the first cell sort and
+ * the first time step.  Synchronises `hip_stream` before returning.
+ * Errors: MPM_E_ARG (descriptor, ids not a permutation, particle outside
+ * the box, non-positive mass or density), MPM_E_WORKSPACE, MPM_E_HIP. */
+int mpm_init(const mpm_desc *desc, const mpm_particles_host *particles,
+             const mpm_obstacle_host *obstacle, void *dev_workspace,
+             size_t workspace_bytes, void *hip_stream, mpm_handle **out);
+
+/* Enqueue n_steps time steps (asynchronous).  Steps after t_end (t_end > 0)
+ * or after a device error are skipped on the device.  n_steps <= 0 runs to
+ * t_end (requires t_end > 0; synchronises once per 64 steps to check).
+ * Errors: MPM_E_ARG, MPM_E_STATE (a device error was already reported),
+ * MPM_E_HIP. */
+int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream);
+
+/* Advance several problems together: every sweep of the step is one launch
+ * whose workgroups cover the tiles of all problems (continuous batching).
+ * Problems must share dim, shape and precision (else MPM_E_UNSUPPORTED).
+ * n_steps[i] steps for problem i; problems that finish early idle.  Up to
+ * 64 problems per call.  Asynchronous.  Errors: MPM_E_ARG,
+ * MPM_E_UNSUPPORTED, MPM_E_STATE, MPM_E_HIP. */
+int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps,
+                   void *hip_stream);
+
+/* Particle fields, returned as double in id order.  Bit i of field_mask
+ * selects field i below; host_out[j] receives the j-th selected field, a
+ * buffer of n_particles * ncomp doubles, component-major.  Synchronises the
+ * stream.  Returns the sticky device error, if any, after copying. */
+enum {
+    MPM_F_X = 0,    /* dim components                                */
+    MPM_F_V = 1,    /* dim                                           */
+    MPM_F_M = 2,
+    MPM_F_RHO = 3,
+    MPM_F_E = 4,    /* specific internal energy                      */
+    MPM_F_P = 5,    /* pressure (gamma-1) rho e                      */
+    MPM_F_Q = 6,    /* artificial pressure of the next step          */
+    MPM_F_G = 7,    /* velocity gradient, dim*dim, row-major         */
+    MPM_F_VOL = 8,  /* M / rho                                       */
+    MPM_F_ID = 9
+};
+int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
+                    void *hip_stream);
+
+/* Grid snapshot of the last completed step as double, node grid x fastest,
+ * component-major (dim comps except MPM_G_M and MPM_G_FLAGS):
+ * raw P2G mass / momentum / force, momentum after the conditions and the
+ * update, force after the conditions, re-mapped momentum after the
+ * conditions, and the node flags.  Allocates a temporary device buffer.
+ * Synchronises the stream. */
+enum { MPM_G_M = 0, MPM_G_P = 1, MPM_G_F = 2, MPM_G_PUPD = 3, MPM_G_P2 = 4,
+       MPM_G_FBC = 5, MPM_G_FLAGS = 6 };
+int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);
+
+/* Time, next and last time step, completed steps and FP64 sums over the
+ * particles: mass, momentum (3), internal energy sum M e, kinetic energy
+ * sum M |v|^2 / 2.  Synchronises the stream.  Any pointer may be NULL.
+ * Returns the sticky device error (MPM_E_NONPHYSICAL / MPM_E_OVERFLOW),
+ * else MPM_OK. */
+int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last,
+               int64_t *step, double conserved[6], void *hip_stream);
+
+/* Diagnostic counters: [0] particles whose cell changed between sort and
+ * use (handled on a slow path), [1] particles clamped back through a wall,
+ * [2] particles recycled at the outflow, [3] fixed-point contributions that
+ * needed the 64-bit conversion path.  Synchronises. */
+int mpm_counters(mpm_handle *h, uint64_t counters[4], void *hip_stream);
+
+/* Per-sweep timing: runs n_steps steps eagerly with a HIP event after each
+ * of the 8 kernels of a step (cell-histogram/grid clear, P2G, G2P + P2G of
+ * the updated momentum, three scan kernels, update + move + scatter, time
+ * step finalize) and writes the average milliseconds per kernel.  The
+ * steps are real steps of the problem.  Synchronises the stream. */
+int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[8], void *hip_stream);
+
+/* Nodes per axis (n+1 for Q1, n+2 for B2; 1 for unused axes). */
+int mpm_grid_shape(const mpm_handle *h, int32_t nodes[3]);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+int mpm_destroy(mpm_handle *h);
+
+/* Static description of a status code. */
+const char *mpm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

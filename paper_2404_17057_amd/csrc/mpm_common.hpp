@@ -1,0 +1,106 @@
+// Internal layout shared by the host orchestration and the gfx950 kernels.
+//
+// One problem lives in one caller-owned device workspace.  Its descriptor
+// (ProbDev) sits at the start of the workspace; the sweeps read it at the
+// start of every workgroup, and the finalize kernel writes the per-step state
+// (t, dt, parity, active, error bits), so that a captured graph of several
+// steps replays without host involvement.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+// -------------------------------------------------------------- precision --
+enum Prec { P_FP64 = 0, P_F32_A64 = 1, P_F32_A32 = 2, P_F32_FIX = 3 };
+
+template <int PREC> struct PrecT;
+template <> struct PrecT<P_FP64>    { using real = double; using acc = double;    static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_A64> { using real = float;  using acc = double;    static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_A32> { using real = float;  using acc = float;     static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_FIX> { using real = float;  using acc = long long; static constexpr bool fixed = true;  };
+
+// ------------------------------------------------------------- constants --
+enum Shape { S_Q1 = 1, S_B2 = 2 };
+enum Face { F_WALL = 0, F_INFLOW = 1, F_OUTFLOW = 2 };
+
+// Node flag bits (static, set at init from the faces and the obstacle mask).
+enum : uint8_t { NF_WALL_X = 1, NF_WALL_Y = 2, NF_WALL_Z = 4, NF_INFLOW = 8, NF_OBST = 16 };
+
+// Sticky error bits.
+enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_WALL = 8u };
+
+// Diagnostic counters (u64).
+enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2, DG_WIDE = 3 };
+
+// Per-tile partial results of the update sweep (doubles).
+enum { PT_VMAX = 0, PT_CMAX = 1, PT_M = 2, PT_MV = 3 /* 3 */, PT_ME = 6, PT_MK = 7, PT_N = 8 };
+
+// Particle fields stored per parity (arrays of `real`).
+enum { PF_X = 0, PF_V = 3, PF_M = 6, PF_RHO = 7, PF_E = 8, PF_G = 9, PF_N = 18 };
+
+// Tile sizes (cells) per dimension: one lane per cell, 256 lanes per group.
+template <int DIM> struct Tile;
+template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1, CELLS = 256; };
+template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4, CELLS = 256; };
+
+constexpr int kBlock = 256;          // threads per workgroup in every sweep
+constexpr int kScanItems = 16;       // cells per thread in the scan
+constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kMaxBatch = 64;        // problems per batched launch
+constexpr int kSweeps = 8;           // kernels per step: zero, p2g, g2p, scan a/b/c, update, finalize
+
+struct ProbDev {
+    // ---- static geometry and parameters (written once at init)
+    int dim, shape, prec, av_form;
+    int n[3];             // cells per axis (1 for unused axes)
+    int nn[3];            // nodes per axis
+    int ntile[3];         // tiles per axis
+    int ntiles;           // product of ntile
+    int nchunks;          // scan chunks
+    long long ncells_pad; // ntiles * cells per tile (size of the key space)
+    long long nnodes;
+    long long np;
+    double lo[3], hi[3], h, inv_h;
+    double gamma, c0, c1, cfl;
+    int face[3][2];
+    double inflow_rho, inflow_p, inflow_e, inflow_u[3], recycle_mass;
+    unsigned long long seed;
+    double t_end;
+    double q_m, q_p, inv_q_m, inv_q_p;   // fixed-point quanta (powers of two)
+    int has_obstacle, pad0;
+
+    // ---- device pointers into the workspace
+    void *part[2][PF_N];      // particle fields, per parity (real*)
+    uint32_t *pid[2];         // particle ids, per parity
+    uint32_t *key, *rank;     // new cell key and rank within the cell (from S2)
+    uint32_t *count;          // per-cell histogram of the new keys
+    uint32_t *offs[2];        // exclusive prefix of counts, per parity (+1 entry)
+    uint32_t *blocksum;       // scan chunk sums
+    void *gA;                 // m, p[d], I[d]: (1 + 2 dim) * nnodes acc words
+    void *gB;                 // p2[d]: dim * nnodes acc words
+    uint8_t *nflag;
+    void *nrm;                // dim * nnodes real, or null
+    double *partials;         // ntiles * PT_N
+    void *zero_base;          // [zero_base, zero_base + zero_bytes) cleared each step
+    long long zero_bytes;
+
+    // ---- per-step state (device-updated)
+    double t, dt, dt_last;
+    long long step, steps_left;
+    int active, parity;
+    uint32_t err, pad1;
+    unsigned long long diag[4];
+    double cons[6];
+};
+
+// Work table of one batched launch: problem i owns workgroups
+// [start[i], start[i+1]).  Passed by value (kernel argument segment).
+struct WorkTab {
+    ProbDev *prob[kMaxBatch];
+    int start[kMaxBatch + 1];
+    int n;
+};
+
+}  // namespace mpm

@@ -1,0 +1,299 @@
+// Device-side building blocks of the MPM step for gfx950.
+#pragma once
+
+#include "mpm_common.hpp"
+
+namespace mpm {
+
+template <int DIM, int SHAPE> struct Geo {
+    static constexpr int W = SHAPE == S_B2 ? 3 : 2;          // nodes per axis in a stencil
+    static constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
+    static constexpr int NX = TX + W - 1, NY = TY + W - 1;   // tile footprint in nodes
+    static constexpr int NZ = DIM == 3 ? TZ + W - 1 : 1;
+    static constexpr int TN = NX * NY * NZ;
+    static constexpr int WP = W * W;                          // stencil nodes per z-slab
+    static constexpr int PASSES = DIM == 3 ? W : 1;           // z-slabs of the stencil
+    static constexpr int CELLS = Tile<DIM>::CELLS;
+};
+
+// ------------------------------------------------------------------ basis --
+// One axis of the basis at reduced coordinate s = (x - lo)/h.  Returns the
+// cell c (first stencil node); w/dw are the values and d/ds derivatives of
+// the W non-zero functions.
+//
+// Q1 (Sec. 2.2): phi_c = 1 - u, phi_{c+1} = u, u = s - c.
+// B2: quadratic B-splines on the clamped knot vector of the cell faces
+// (0,0,0,1,...,n-1,n,n,n).  In an interior cell the three functions are the
+// uniform pieces (1-u)^2/2, 1/2 + u(1-u), u^2/2.  The knot multiplicity
+// changes the pieces in the first cell, (1-u)^2, u(2 - 3u/2), u^2/2, and
+// symmetrically in the last cell, so that only the first (last) function is
+// non-zero on the domain face.
+template <int SHAPE, typename R>
+__device__ __forceinline__ int basis1(R s, int n, R w[3], R dw[3]) {
+    int c = (int)floor(s);
+    c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+    const R u = s - (R)c;
+    const R v = (R)1 - u;
+    if constexpr (SHAPE == S_Q1) {
+        w[0] = v;  dw[0] = (R)-1;
+        w[1] = u;  dw[1] = (R)1;
+    } else {
+        const R hv2 = (R)0.5 * v * v, hu2 = (R)0.5 * u * u;
+        if (c == 0) {
+            w[0] = v * v;                  dw[0] = (R)-2 * v;
+            w[1] = u * ((R)2 - (R)1.5 * u); dw[1] = (R)2 - (R)3 * u;
+            w[2] = hu2;                     dw[2] = u;
+        } else if (c == n - 1) {
+            w[0] = hv2;                     dw[0] = -v;
+            w[1] = v * ((R)2 - (R)1.5 * v); dw[1] = (R)1 - (R)3 * u;
+            w[2] = u * u;                   dw[2] = (R)2 * u;
+        } else {
+            w[0] = hv2;                     dw[0] = -v;
+            w[1] = (R)0.5 + u * v;          dw[1] = (R)1 - (R)2 * u;
+            w[2] = hu2;                     dw[2] = u;
+        }
+    }
+    return c;
+}
+
+// Particle stencil: per-axis cells, weights and derivatives.
+template <int DIM, int SHAPE, typename R> struct Stencil {
+    int c[3];
+    R w[3][3], dw[3][3];
+};
+
+template <int DIM, int SHAPE, typename R>
+__device__ __forceinline__ void make_stencil(const ProbDev *P, const R x[3], Stencil<DIM, SHAPE, R> &st) {
+    const R inv_h = (R)P->inv_h;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const R s = (x[a] - (R)P->lo[a]) * inv_h;
+        st.c[a] = basis1<SHAPE, R>(s, P->n[a], st.w[a], st.dw[a]);
+    }
+    if constexpr (DIM == 2) st.c[2] = 0;
+}
+
+// ---------------------------------------------------------- constitutive --
+template <typename R> __device__ __forceinline__ R eos_p(R gamma, R rho, R e) {
+    return (gamma - (R)1) * rho * e;                 // perfect gas (Sec. 2.1)
+}
+template <typename R> __device__ __forceinline__ R sound(R gamma, R rho, R p) {
+    const R c2 = gamma * p / rho;
+    return c2 > (R)0 ? sqrt(c2) : (R)0;
+}
+// Artificial pressure (Sec. 2.1, eq. muart), only for div v < 0.
+template <typename R>
+__device__ __forceinline__ R art_visc(int form, R c0, R c1, R gamma, R h, R rho, R p, R D) {
+    if (!(D < (R)0)) return (R)0;
+    const R c = sound(gamma, rho, p);
+    if (form == 1) return c0 * rho * (h * D) * (h * D) - c1 * rho * h * c * D;
+    const R r = rho * h * D;
+    return c0 * r * r - c1 * h * c * D;
+}
+
+// -------------------------------------------------------- fixed point --
+// Scaled contribution -> int64, round to nearest even.  The common case fits
+// 32 bits (one v_cvt_i32_f32); wider values take the exact 64-bit path;
+// beyond 2^62 the overflow bit is raised.
+__device__ __forceinline__ long long to_fix(float y, uint32_t &flags) {
+    const float r = rintf(y);
+    if (fabsf(r) < 2147483648.0f) return (long long)(int)r;
+    if (!(fabsf(r) < 4.611686018427388e18f)) { flags |= ERR_OVERFLOW; return 0; }
+    flags |= 0x100u;                                // diagnostic: wide path used
+    return (long long)r;
+}
+
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::acc to_acc(typename PrecT<PREC>::real y, uint32_t &flags) {
+    if constexpr (PrecT<PREC>::fixed) return to_fix(y, flags);
+    else return (typename PrecT<PREC>::acc)y;
+}
+
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::real from_acc(typename PrecT<PREC>::acc a, double q, uint32_t &flags) {
+    using R = typename PrecT<PREC>::real;
+    if constexpr (PrecT<PREC>::fixed) {
+        const long long lim = 4611686018427387904LL;        // 2^62
+        if (a >= lim || a <= -lim) flags |= ERR_OVERFLOW;
+        return (R)a * (R)q;                                 // q is a power of two
+    } else {
+        (void)q;
+        return (R)a;
+    }
+}
+
+// -------------------------------------------------------------- atomics --
+__device__ __forceinline__ void lds_add(long long *p, long long v) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void lds_add(double *p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
+
+__device__ __forceinline__ void glb_add(long long *p, long long v) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+__device__ __forceinline__ void glb_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void glb_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// ------------------------------------------------------------ boundary --
+// Conditions on one nodal vector (Sec. 3 steps (iii), (vii)): obstacle
+// projection u -= ((u.n - |u.n|)/2) n (eqs. normali1/2), then the normal
+// component at wall faces, then the inflow state (momentum m u_in, force 0).
+template <int DIM, typename R>
+__device__ __forceinline__ void node_bc(const ProbDev *P, uint8_t fl, long long node, R m, R u[3], bool is_force) {
+    if (fl & NF_OBST) {
+        const R *nrm = (const R *)P->nrm;
+        R n[3] = {0, 0, 0};
+        R un = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) { n[a] = nrm[a * P->nnodes + node]; un += u[a] * n[a]; }
+        const R k = (R)0.5 * (un - fabs(un));
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u[a] -= k * n[a];
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        if (fl & (NF_WALL_X << a)) u[a] = (R)0;
+    if (fl & NF_INFLOW) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) u[a] = is_force ? (R)0 : m * (R)P->inflow_u[a];
+    }
+}
+
+// ------------------------------------------------------ recycling hash --
+// SplitMix64 output for state z (Steele, Lea, Flood 2014): golden-ratio
+// increment, then the finaliser.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Postponed move X' = X + dt Vbar (Sec. 3 step (ix)).  A particle crossing an
+// OUTFLOW high-x face re-enters at x - L_x with its transverse coordinates
+// drawn from splitmix64(seed ^ step<<32 ^ id ^ (a-1)<<56) (reading of the
+// random inflow cell of Sec. 4.1); any other exit is clamped and counted.
+// Returns 1 when the particle was recycled, 2 when clamped, 0 otherwise.
+template <int DIM, typename R>
+__device__ __forceinline__ int advect(const ProbDev *P, R x[3], const R vbar[3], R dt, uint32_t id) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) x[a] = x[a] + dt * vbar[a];
+    if (P->face[0][1] == F_OUTFLOW && x[0] >= (R)P->hi[0]) {
+        x[0] = x[0] - (R)(P->hi[0] - P->lo[0]);
+#pragma unroll
+        for (int a = 1; a < DIM; ++a) {
+            const unsigned long long word = P->seed ^ ((unsigned long long)P->step << 32) ^
+                                            (unsigned long long)id ^ ((unsigned long long)(a - 1) << 56);
+            const double u = (double)(splitmix64(word) >> 11) * 0x1.0p-53;
+            x[a] = (R)(P->lo[a] + (P->hi[a] - P->lo[a]) * u);
+        }
+        return 1;
+    }
+    int clamped = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const R lo = (R)P->lo[a], hi = (R)P->hi[a];
+        if (x[a] < lo) { x[a] = lo; clamped = 2; }
+        else if (x[a] >= hi) {
+            R in = (R)(P->hi[a] - 1e-9 * (P->hi[a] - P->lo[a]));
+            if (in >= hi) in = nextafter(hi, lo);
+            x[a] = in;
+            clamped = 2;
+        }
+    }
+    return clamped;
+}
+
+// Tile-major cell key of a cell triple.
+template <int DIM>
+__device__ __forceinline__ uint32_t cell_key(const ProbDev *P, const int c[3]) {
+    constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
+    const int tx = c[0] / TX, ty = c[1] / TY, tz = DIM == 3 ? c[2] / TZ : 0;
+    const int lx = c[0] - tx * TX, ly = c[1] - ty * TY, lz = DIM == 3 ? c[2] - tz * TZ : 0;
+    const long long tile = ((long long)tz * P->ntile[1] + ty) * P->ntile[0] + tx;
+    return (uint32_t)(tile * Tile<DIM>::CELLS + (lz * TY + ly) * TX + lx);
+}
+
+// Cell triple of a position (the first stencil node of the basis).
+template <int DIM, typename R>
+__device__ __forceinline__ void cell_of(const ProbDev *P, const R x[3], int c[3]) {
+    const R inv_h = (R)P->inv_h;
+    c[2] = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const R s = (x[a] - (R)P->lo[a]) * inv_h;
+        int ca = (int)floor(s);
+        c[a] = ca < 0 ? 0 : (ca > P->n[a] - 1 ? P->n[a] - 1 : ca);
+    }
+}
+
+// ----------------------------------------------------------- node staging --
+// Nodal values the gather sweeps need, computed from the integer / float
+// accumulators with the boundary conditions applied:
+//   vstar = (p + I)/m  with p, I after the conditions (I = dt f, the impulse)
+//   dvel  = I/m        (the velocity increment dt f/m)
+//   v2    = p2/m       with p2 after the momentum conditions
+// Nodes without mass give 0.
+template <int DIM, int PREC>
+__device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
+                                        typename PrecT<PREC>::real vstar[3],
+                                        typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
+    using R = typename PrecT<PREC>::real;
+    using A = typename PrecT<PREC>::acc;
+    const A *g = (const A *)P->gA;
+    const long long NN = P->nnodes;
+    const R m = from_acc<PREC>(g[node], P->q_m, flags);
+    R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        p[a] = from_acc<PREC>(g[(1 + a) * NN + node], P->q_p, flags);
+        I[a] = from_acc<PREC>(g[(1 + DIM + a) * NN + node], P->q_p, flags);
+    }
+    const uint8_t fl = P->nflag[node];
+    if (fl) {
+        node_bc<DIM, R>(P, fl, node, m, p, false);
+        node_bc<DIM, R>(P, fl, node, m, I, true);
+    }
+    const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        vstar[a] = (p[a] + I[a]) * inv_m;
+        dvel[a] = I[a] * inv_m;
+    }
+}
+
+template <int DIM, int PREC>
+__device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
+                                        typename PrecT<PREC>::real v2[3], uint32_t &flags) {
+    using R = typename PrecT<PREC>::real;
+    using A = typename PrecT<PREC>::acc;
+    const A *gA = (const A *)P->gA;
+    const A *gB = (const A *)P->gB;
+    const long long NN = P->nnodes;
+    const R m = from_acc<PREC>(gA[node], P->q_m, flags);
+    R p[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) p[a] = from_acc<PREC>(gB[a * NN + node], P->q_p, flags);
+    const uint8_t fl = P->nflag[node];
+    if (fl) node_bc<DIM, R>(P, fl, node, m, p, false);
+    const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v2[a] = p[a] * inv_m;
+}
+
+__device__ __forceinline__ long long node_index(const ProbDev *P, int ix, int iy, int iz) {
+    return (long long)ix + (long long)P->nn[0] * ((long long)iy + (long long)P->nn[1] * iz);
+}
+
+// Problem owning workgroup b of a batched launch.
+__device__ __forceinline__ int find_prob(const WorkTab &wt, int b) {
+    int lo = 0, hi = wt.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wt.start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace mpm

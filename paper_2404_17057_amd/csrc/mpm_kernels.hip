@@ -1,0 +1,984 @@
+// gfx950 kernels of the MPM step.
+//
+// Every sweep is a batched launch: workgroup b belongs to problem
+// find_prob(wt, b) and covers one tile of cells (or one chunk of the key
+// space).  Particles are kept sorted by the tile-major key of their cell, so
+// the particles of a tile are one contiguous range.
+//
+// Per step (all problems of a batch together):
+//   k_zero      clear the grid accumulators and the cell histogram
+//   k_p2g       S1: P2G mass, momentum, impulse dt*f        (Sec. 3 (ii))
+//   k_g2p       S2: conditions + update on the tile load, G2P, FLIP velocity
+//               update, new cell key and rank, P2G of M V'   (Sec. 3 (iii)-(vi))
+//   k_scan_*    exclusive prefix of the new cell histogram
+//   k_update    S3: conditions on p2 on the tile load, G2PD, energy /
+//               density update, move, recycling, scatter into the new sorted
+//               order, per-tile CFL maxima and FP64 sums (Sec. 3 (vii)-(xi))
+//   k_finalize  dt of the next step, t, conserved sums, parity flip (xii)
+//
+// P2G (S1, S2): one lane per cell.  The lane walks the particles of its
+// cell and sums their contributions to the cell's stencil nodes in
+// registers (a particle-level pre-reduction: lanes of one instruction touch
+// distinct nodes), then adds the sums into an LDS tile of the footprint
+// nodes, and the tile is added to the global grid with one atomic per
+// non-zero node value.  In the fixed-point precision every contribution is
+// rounded to an int64 quantum before any addition, so all sums are exact
+// and independent of order.
+#include "mpm_device.hpp"
+
+namespace mpm {
+
+// ------------------------------------------------------------------- zero --
+__global__ __launch_bounds__(kBlock) void k_zero(WorkTab wt) {
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int b = blockIdx.x - wt.start[pi];
+    const int nb = wt.start[pi + 1] - wt.start[pi];
+    uint4 *base = (uint4 *)P->zero_base;
+    const long long n16 = P->zero_bytes / 16;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (long long i = (long long)b * kBlock + threadIdx.x; i < n16; i += (long long)nb * kBlock)
+        base[i] = z;
+}
+
+// Number of zero-kernel workgroups for a problem.
+int zero_blocks(const ProbDev &h) {
+    long long n16 = h.zero_bytes / 16;
+    long long nb = (n16 + kBlock * 8 - 1) / (kBlock * 8);
+    return (int)(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
+}
+
+// Tile coordinates of tile t and this lane's cell.
+template <int DIM>
+__device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], int lc[3]) {
+    constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
+    const int tx = t % P->ntile[0];
+    const int ty = (t / P->ntile[0]) % P->ntile[1];
+    const int tz = DIM == 3 ? t / (P->ntile[0] * P->ntile[1]) : 0;
+    c0[0] = tx * TX; c0[1] = ty * TY; c0[2] = tz * TZ;
+    const int l = threadIdx.x;
+    lc[0] = l % TX; lc[1] = (l / TX) % TY; lc[2] = DIM == 3 ? l / (TX * TY) : 0;
+}
+
+// -------------------------------------------------------------------- S1 --
+template <int DIM, int SHAPE, int PREC>
+__global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    using A = typename PrecT<PREC>::acc;
+    constexpr int NQ = 1 + 2 * DIM;
+    constexpr int W = G::W;
+    __shared__ A tile[NQ * G::TN];
+
+    const int pi = find_prob(wt, blockIdx.x);
+    const ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int t = blockIdx.x - wt.start[pi];
+
+    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) tile[i] = (A)0;
+    __syncthreads();
+
+    int c0[3], lc[3];
+    tile_cell<DIM>(P, t, c0, lc);
+    int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
+    bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
+    const int par = P->parity;
+    const uint32_t *off = P->offs[par];
+    const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
+    const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
+
+    const R *X[3], *V[3], *Gd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        X[a] = (const R *)P->part[par][PF_X + a];
+        V[a] = (const R *)P->part[par][PF_V + a];
+        Gd[a] = (const R *)P->part[par][PF_G + a * DIM + a];
+    }
+    const R *Mp = (const R *)P->part[par][PF_M];
+    const R *RHOp = (const R *)P->part[par][PF_RHO];
+    const R *Ep = (const R *)P->part[par][PF_E];
+    const R gam = (R)P->gamma, c0v = (R)P->c0, c1v = (R)P->c1, h = (R)P->h, inv_h = (R)P->inv_h;
+    const R dt = (R)P->dt;
+    const R sm = PrecT<PREC>::fixed ? (R)P->inv_q_m : (R)1;
+    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
+    const int form = P->av_form;
+    uint32_t flags = 0;
+    unsigned long long mismatch = 0;
+
+#pragma unroll 1
+    for (int pass = 0; pass < G::PASSES; ++pass) {
+        A acc[G::WP][NQ];
+#pragma unroll
+        for (int s = 0; s < G::WP; ++s)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[s][q] = (A)0;
+
+#pragma unroll 1
+        for (uint32_t k = beg; k < end; ++k) {
+            R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) { x[a] = X[a][k]; v[a] = V[a][k]; }
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(P, x, st);
+            const R M = Mp[k], rho = RHOp[k], e = Ep[k];
+            R D = 0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) D += Gd[a][k];
+            const R p = eos_p(gam, rho, e);
+            const R q = art_visc(form, c0v, c1v, gam, h, rho, p, D);
+            const R Ms = M * sm;
+            R MVs[3];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) MVs[a] = M * v[a] * sp;
+            // impulse scale dt (P+Q) (M/rho) / h; the 1/h turns d/ds into d/dx
+            const R Fs = dt * (p + q) * (M / rho) * inv_h * sp;
+
+            bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+            if (!own) {
+                // Cell changed between sort and use: add this particle's
+                // contributions straight to the global grid (slow path).
+                if (pass == 0) {
+                    ++mismatch;
+                    A *g = (A *)P->gA;
+                    const long long NN = P->nnodes;
+                    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+                        for (int jy = 0; jy < W; ++jy)
+                            for (int jx = 0; jx < W; ++jx) {
+                                const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
+                                const R w = st.w[0][jx] * st.w[1][jy] * wz;
+                                R gr[3];
+                                gr[0] = st.dw[0][jx] * st.w[1][jy] * wz;
+                                gr[1] = st.w[0][jx] * st.dw[1][jy] * wz;
+                                gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] : (R)0;
+                                const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy,
+                                                                  DIM == 3 ? st.c[2] + jz : 0);
+                                glb_add(&g[node], to_acc<PREC>(Ms * w, flags));
+                                for (int a = 0; a < DIM; ++a) {
+                                    glb_add(&g[(1 + a) * NN + node], to_acc<PREC>(MVs[a] * w, flags));
+                                    glb_add(&g[(1 + DIM + a) * NN + node], to_acc<PREC>(Fs * gr[a], flags));
+                                }
+                            }
+                }
+                continue;
+            }
+            const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
+            const R dwz = DIM == 3 ? st.dw[2][pass] : (R)0;
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+                    const int s = jy * W + jx;
+                    const R wxy = st.w[0][jx] * st.w[1][jy];
+                    const R w = wxy * wz;
+                    acc[s][0] += to_acc<PREC>(Ms * w, flags);
+                    R gr[3];
+                    gr[0] = st.dw[0][jx] * st.w[1][jy] * wz;
+                    gr[1] = st.w[0][jx] * st.dw[1][jy] * wz;
+                    gr[2] = wxy * dwz;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        acc[s][1 + a] += to_acc<PREC>(MVs[a] * w, flags);
+                        acc[s][1 + DIM + a] += to_acc<PREC>(Fs * gr[a], flags);
+                    }
+                }
+        }
+        if (end > beg) {
+            const int lz = DIM == 3 ? lc[2] + pass : 0;
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+                    const int s = jy * W + jx;
+                    const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (acc[s][q] != (A)0) lds_add(&tile[q * G::TN + li], acc[s][q]);
+                }
+        }
+    }
+    __syncthreads();
+
+    // Flush the footprint to the global grid.
+    A *g = (A *)P->gA;
+    const long long NN = P->nnodes;
+    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) {
+        const A val = tile[i];
+        if (val == (A)0) continue;
+        const int q = i / G::TN, li = i - q * G::TN;
+        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
+        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
+        if (gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
+        glb_add(&g[q * NN + node_index(P, gx, gy, gz)], val);
+    }
+    if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
+    if (flags & 0x100u) atomicAdd((unsigned long long *)&P->diag[DG_WIDE], 1ull);
+    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
+}
+
+// Stage the tile footprint of nodes: fields[f * TN + li].
+template <int DIM, int SHAPE, int PREC, bool WITH_B>
+__device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
+                                           typename PrecT<PREC>::real *lds, uint32_t &flags) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    for (int li = threadIdx.x; li < G::TN; li += kBlock) {
+        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
+        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
+        R vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+        if (gx < P->nn[0] && gy < P->nn[1] && gz < P->nn[2]) {
+            const long long node = node_index(P, gx, gy, gz);
+            if constexpr (WITH_B) {
+                R unused[3];
+                stage_A<DIM, PREC>(P, node, vs, unused, flags);
+                stage_B<DIM, PREC>(P, node, dv, flags);
+            } else {
+                stage_A<DIM, PREC>(P, node, vs, dv, flags);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            lds[a * G::TN + li] = vs[a];
+            lds[(DIM + a) * G::TN + li] = dv[a];
+        }
+    }
+}
+
+// G2P of two staged vector fields at one particle: out0 = sum w f0,
+// out1 = sum w f1 (f0 = fields 0..DIM-1, f1 = DIM..2DIM-1).  The node order
+// is fixed, so the same particle gives the same bits in every sweep.
+template <int DIM, int SHAPE, typename R>
+__device__ __forceinline__ void g2p_two(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3],
+                                        R out0[3], R out1[3]) {
+    using G = Geo<DIM, SHAPE>;
+    constexpr int W = G::W;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { out0[a] = 0; out1[a] = 0; }
+#pragma unroll
+    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll
+        for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < W; ++jx) {
+                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
+                const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    out0[a] += w * lds[a * G::TN + li];
+                    out1[a] += w * lds[(DIM + a) * G::TN + li];
+                }
+            }
+}
+
+// Same sums read straight from the global grid (slow path for a particle
+// whose stencil leaves the staged footprint).
+template <int DIM, int SHAPE, int PREC, bool WITH_B>
+__device__ __forceinline__ void g2p_two_global(const ProbDev *P, const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
+                                               typename PrecT<PREC>::real out0[3], typename PrecT<PREC>::real out1[3],
+                                               uint32_t &flags) {
+    using R = typename PrecT<PREC>::real;
+    constexpr int W = Geo<DIM, SHAPE>::W;
+    for (int a = 0; a < 3; ++a) { out0[a] = 0; out1[a] = 0; }
+    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+        for (int jy = 0; jy < W; ++jy)
+            for (int jx = 0; jx < W; ++jx) {
+                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
+                const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
+                R f0[3], f1[3], d2[3];
+                if constexpr (WITH_B) { stage_A<DIM, PREC>(P, node, f0, d2, flags); stage_B<DIM, PREC>(P, node, f1, flags); }
+                else stage_A<DIM, PREC>(P, node, f0, f1, flags);
+                for (int a = 0; a < DIM; ++a) { out0[a] += w * f0[a]; out1[a] += w * f1[a]; }
+            }
+}
+
+// -------------------------------------------------------------------- S2 --
+template <int DIM, int SHAPE, int PREC>
+__global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    using A = typename PrecT<PREC>::acc;
+    constexpr int W = G::W;
+    __shared__ R stage[2 * DIM * G::TN];
+    __shared__ A tile[DIM * G::TN];
+
+    const int pi = find_prob(wt, blockIdx.x);
+    const ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int t = blockIdx.x - wt.start[pi];
+    int c0[3], lc[3];
+    tile_cell<DIM>(P, t, c0, lc);
+    uint32_t flags = 0;
+
+    for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (A)0;
+    stage_tile<DIM, SHAPE, PREC, false>(P, c0, stage, flags);
+    __syncthreads();
+
+    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
+    const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
+    const int par = P->parity;
+    const uint32_t *off = P->offs[par];
+    const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
+    const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
+
+    R *X[3], *V[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        X[a] = (R *)P->part[par][PF_X + a];
+        V[a] = (R *)P->part[par][PF_V + a];
+    }
+    const R *Mp = (const R *)P->part[par][PF_M];
+    const uint32_t *ids = P->pid[par];
+    const R dt = (R)P->dt;
+    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
+    unsigned long long mismatch = 0;
+
+#pragma unroll 1
+    for (int pass = 0; pass < G::PASSES; ++pass) {
+        A acc[G::WP][DIM];
+#pragma unroll
+        for (int s = 0; s < G::WP; ++s)
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) acc[s][a] = (A)0;
+
+#pragma unroll 1
+        for (uint32_t k = beg; k < end; ++k) {
+            R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) { x[a] = X[a][k]; v[a] = V[a][k]; }
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(P, x, st);
+            const R M = Mp[k];
+            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+            if (pass == 0) {
+                R vbar[3], dv[3];
+                if (own) g2p_two<DIM, SHAPE, R>(stage, st, lc, vbar, dv);
+                else { ++mismatch; g2p_two_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, flags); }
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) { v[a] = v[a] + dv[a]; V[a][k] = v[a]; }
+                // New position (not stored: the update sweep recomputes it
+                // from the same staged values) -> new cell key and rank.
+                R xn[3] = {x[0], x[1], x[2]};
+                advect<DIM, R>(P, xn, vbar, dt, ids[k]);
+                int cn[3];
+                cell_of<DIM, R>(P, xn, cn);
+                const uint32_t nk = cell_key<DIM>(P, cn);
+                P->key[k] = nk;
+                P->rank[k] = atomicAdd(&P->count[nk], 1u);
+            }
+            const R Ms = M * sp;
+            if (!own) {
+                if (pass == 0) {
+                    A *g = (A *)P->gB;
+                    const long long NN = P->nnodes;
+                    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+                        for (int jy = 0; jy < W; ++jy)
+                            for (int jx = 0; jx < W; ++jx) {
+                                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
+                                const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy,
+                                                                  DIM == 3 ? st.c[2] + jz : 0);
+                                for (int a = 0; a < DIM; ++a)
+                                    glb_add(&g[a * NN + node], to_acc<PREC>(Ms * v[a] * w, flags));
+                            }
+                }
+                continue;
+            }
+            const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+                    const R w = st.w[0][jx] * st.w[1][jy] * wz;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_acc<PREC>(Ms * v[a] * w, flags);
+                }
+        }
+        if (end > beg) {
+            const int lz = DIM == 3 ? lc[2] + pass : 0;
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+                    const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a)
+                        if (acc[jy * W + jx][a] != (A)0) lds_add(&tile[a * G::TN + li], acc[jy * W + jx][a]);
+                }
+        }
+    }
+    __syncthreads();
+
+    A *g = (A *)P->gB;
+    const long long NN = P->nnodes;
+    for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) {
+        const A val = tile[i];
+        if (val == (A)0) continue;
+        const int q = i / G::TN, li = i - q * G::TN;
+        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
+        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
+        if (gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
+        glb_add(&g[q * NN + node_index(P, gx, gy, gz)], val);
+    }
+    if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
+    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
+}
+
+// ------------------------------------------------------------------ scan --
+// Exclusive prefix of the cell histogram into offs[parity ^ 1].
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    // Hillis-Steele over the 256 thread totals in LDS.
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    total = sh[kBlock - 1];
+    const uint32_t incl = sh[threadIdx.x];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_a(WorkTab wt) {
+    __shared__ uint32_t sh[kBlock];
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int ch = blockIdx.x - wt.start[pi];
+    const long long base = (long long)ch * kScanChunk + (long long)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const long long c = base + i;
+        if (c < P->ncells_pad) s += P->count[c];
+    }
+    uint32_t total;
+    block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0) P->blocksum[ch] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_b(WorkTab wt) {
+    __shared__ uint32_t sh[kBlock];
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < P->nchunks; b0 += kBlock) {
+        const int i = b0 + threadIdx.x;
+        const uint32_t v = i < P->nchunks ? P->blocksum[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(v, sh, total);
+        if (i < P->nchunks) P->blocksum[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_c(WorkTab wt) {
+    __shared__ uint32_t sh[kBlock];
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int ch = blockIdx.x - wt.start[pi];
+    uint32_t *out = P->offs[P->parity ^ 1];
+    const long long base = (long long)ch * kScanChunk + (long long)threadIdx.x * kScanItems;
+    uint32_t vals[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const long long c = base + i;
+        vals[i] = c < P->ncells_pad ? P->count[c] : 0u;
+        s += vals[i];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, total) + P->blocksum[ch];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const long long c = base + i;
+        if (c < P->ncells_pad) out[c] = run;
+        run += vals[i];
+    }
+    if (ch == P->nchunks - 1 && threadIdx.x == 0) out[P->ncells_pad] = (uint32_t)P->np;
+}
+
+// -------------------------------------------------------------------- S3 --
+template <typename T>
+__device__ __forceinline__ T block_reduce_sum(T v, T *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const T r = sh[0];
+    __syncthreads();
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T block_reduce_max(T v, T *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const T r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <int DIM, int SHAPE, int PREC>
+__global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    constexpr int W = G::W;
+    __shared__ R stage[2 * DIM * G::TN];
+    __shared__ double red[kBlock];
+
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int t = blockIdx.x - wt.start[pi];
+    int c0[3], lc[3];
+    tile_cell<DIM>(P, t, c0, lc);
+    uint32_t flags = 0;
+    stage_tile<DIM, SHAPE, PREC, true>(P, c0, stage, flags);
+    __syncthreads();
+
+    const int par = P->parity, npar = par ^ 1;
+    const uint32_t *off = P->offs[par];
+    const uint32_t *noff = P->offs[npar];
+    const uint32_t pbeg = off[(uint32_t)t * G::CELLS], pend = off[(uint32_t)(t + 1) * G::CELLS];
+    const R dt = (R)P->dt;
+    const double dtd = P->dt;
+    const R gam = (R)P->gamma, c0v = (R)P->c0, c1v = (R)P->c1, h = (R)P->h, inv_h = (R)P->inv_h;
+    const int form = P->av_form;
+
+    double vmax = 0, cmax = 0, sM = 0, sMV[3] = {0, 0, 0}, sME = 0, sMK = 0;
+    unsigned long long n_mis = 0, n_rec = 0, n_wall = 0;
+
+    for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
+        R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            x[a] = ((const R *)P->part[par][PF_X + a])[k];
+            v[a] = ((const R *)P->part[par][PF_V + a])[k];
+        }
+        R M = ((const R *)P->part[par][PF_M])[k];
+        const R rho = ((const R *)P->part[par][PF_RHO])[k];
+        const R e = ((const R *)P->part[par][PF_E])[k];
+        R Dprev = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) Dprev += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
+        const uint32_t id = P->pid[par][k];
+
+        Stencil<DIM, SHAPE, R> st;
+        make_stencil<DIM, SHAPE, R>(P, x, st);
+        int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+        const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
+                            (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
+
+        // G2PD of v2 (velocity gradient) and G2P of vstar (Vbar)
+        R Gm[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Gm[c] = 0;
+        R vbar[3] = {0, 0, 0};
+        if (inside) {
+#pragma unroll
+            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx) {
+                        const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
+                        R gr[3];
+                        gr[0] = st.dw[0][jx] * st.w[1][jy] * wz * inv_h;
+                        gr[1] = st.w[0][jx] * st.dw[1][jy] * wz * inv_h;
+                        gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] * inv_h : (R)0;
+                        const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            const R va = stage[(DIM + a) * G::TN + li];
+#pragma unroll
+                            for (int b = 0; b < DIM; ++b) Gm[a * DIM + b] += va * gr[b];
+                        }
+                    }
+            R dummy[3];
+            g2p_two<DIM, SHAPE, R>(stage, st, l0, vbar, dummy);
+        } else {
+            ++n_mis;
+            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+                for (int jy = 0; jy < W; ++jy)
+                    for (int jx = 0; jx < W; ++jx) {
+                        const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
+                        R gr[3];
+                        gr[0] = st.dw[0][jx] * st.w[1][jy] * wz * inv_h;
+                        gr[1] = st.w[0][jx] * st.dw[1][jy] * wz * inv_h;
+                        gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] * inv_h : (R)0;
+                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
+                        R v2n[3];
+                        stage_B<DIM, PREC>(P, node, v2n, flags);
+                        for (int a = 0; a < DIM; ++a)
+                            for (int b = 0; b < DIM; ++b) Gm[a * DIM + b] += v2n[a] * gr[b];
+                    }
+            R dummy[3];
+            g2p_two_global<DIM, SHAPE, PREC, false>(P, st, vbar, dummy, flags);
+        }
+
+        R D = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) D += Gm[a * DIM + a];
+        const R p = eos_p(gam, rho, e);
+        const R q = art_visc(form, c0v, c1v, gam, h, rho, p, Dprev);
+        const R J = (R)1 + dt * D;
+        if (!(J > (R)0)) flags |= ERR_NONPHYS;
+        // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.
+        double en = (double)e - dtd * ((double)p + (double)q) * (double)D / (double)rho;
+        R rhon = rho / J;
+        R En = (R)en;
+
+        const int mv = advect<DIM, R>(P, x, vbar, dt, id);
+        if (mv == 1) {
+            ++n_rec;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) v[a] = (R)P->inflow_u[a];
+            rhon = (R)P->inflow_rho;
+            En = (R)P->inflow_e;
+            M = (R)P->recycle_mass;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) Gm[c] = 0;
+        } else if (mv == 2) {
+            ++n_wall;
+        }
+        if (!isfinite((double)En) || !isfinite((double)rhon)) flags |= ERR_NONFINITE;
+
+        const uint32_t slot = noff[P->key[k]] + P->rank[k];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ((R *)P->part[npar][PF_X + a])[slot] = x[a];
+            ((R *)P->part[npar][PF_V + a])[slot] = v[a];
+        }
+        ((R *)P->part[npar][PF_M])[slot] = M;
+        ((R *)P->part[npar][PF_RHO])[slot] = rhon;
+        ((R *)P->part[npar][PF_E])[slot] = En;
+#pragma unroll
+        for (int c = 0; c < DIM * DIM; ++c) ((R *)P->part[npar][PF_G + c])[slot] = Gm[c];
+        P->pid[npar][slot] = id;
+
+        // CFL maxima and FP64 sums of the new state
+        double v2 = 0, vb2 = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            v2 += (double)v[a] * (double)v[a];
+            vb2 += (double)vbar[a] * (double)vbar[a];
+            sMV[a] += (double)M * (double)v[a];
+        }
+        vmax = fmax(vmax, fmax(sqrt(v2), sqrt(vb2)));
+        const R pn = eos_p(gam, rhon, En);
+        cmax = fmax(cmax, (double)sound(gam, rhon, pn));
+        sM += (double)M;
+        sME += (double)M * (double)En;
+        sMK += 0.5 * (double)M * v2;
+    }
+
+    double *pt = P->partials + (long long)t * PT_N;
+    const double r0 = block_reduce_max(vmax, red);
+    const double r1 = block_reduce_max(cmax, red);
+    const double r2 = block_reduce_sum(sM, red);
+    double rv[3];
+    for (int a = 0; a < 3; ++a) rv[a] = block_reduce_sum(sMV[a], red);
+    const double r6 = block_reduce_sum(sME, red);
+    const double r7 = block_reduce_sum(sMK, red);
+    if (threadIdx.x == 0) {
+        pt[PT_VMAX] = r0; pt[PT_CMAX] = r1; pt[PT_M] = r2;
+        pt[PT_MV] = rv[0]; pt[PT_MV + 1] = rv[1]; pt[PT_MV + 2] = rv[2];
+        pt[PT_ME] = r6; pt[PT_MK] = r7;
+    }
+    if (flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW))
+        atomicOr((uint32_t *)&P->err, flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW));
+    if (n_mis) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], n_mis);
+    if (n_rec) atomicAdd((unsigned long long *)&P->diag[DG_RECYCLE], n_rec);
+    if (n_wall) atomicAdd((unsigned long long *)&P->diag[DG_WALL], n_wall);
+}
+
+// -------------------------------------------------------------- finalize --
+// One workgroup per problem: per-tile partials -> CFL time step of the next
+// step (Sec. 2.2, CFL; Sec. 3 (xi)-(xii)), time, conserved sums, parity.
+__device__ void finalize_problem(ProbDev *P, bool advance) {
+    __shared__ double red[kBlock];
+    double vmax = 0, cmax = 0, s[6] = {0, 0, 0, 0, 0, 0};
+    for (int tt = threadIdx.x; tt < P->ntiles; tt += kBlock) {
+        const double *pt = P->partials + (long long)tt * PT_N;
+        vmax = fmax(vmax, pt[PT_VMAX]);
+        cmax = fmax(cmax, pt[PT_CMAX]);
+        s[0] += pt[PT_M];
+        s[1] += pt[PT_MV]; s[2] += pt[PT_MV + 1]; s[3] += pt[PT_MV + 2];
+        s[4] += pt[PT_ME]; s[5] += pt[PT_MK];
+    }
+    vmax = block_reduce_max(vmax, red);
+    cmax = block_reduce_max(cmax, red);
+    double tot[6];
+    for (int c = 0; c < 6; ++c) tot[c] = block_reduce_sum(s[c], red);
+    if (threadIdx.x == 0) {
+        if (advance) {
+            P->dt_last = P->dt;
+            P->t = P->t + P->dt;
+            P->step += 1;
+            P->steps_left -= 1;
+            P->parity ^= 1;
+        }
+        double dtn = (vmax + cmax > 0.0) ? P->cfl * P->h / (vmax + cmax) : 0.0;
+        if (P->t_end > 0.0) {
+            const double rest = P->t_end - P->t;
+            if (rest < dtn) dtn = rest;
+            if (dtn < 0.0) dtn = 0.0;
+        }
+        P->dt = dtn;
+        for (int c = 0; c < 6; ++c) P->cons[c] = tot[c];
+        P->active = (P->steps_left > 0 && P->err == 0 && dtn > 0.0 &&
+                     (P->t_end <= 0.0 || P->t < P->t_end)) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(WorkTab wt) {
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    finalize_problem(P, true);
+}
+
+// Arm problems for a run of steps: steps_left and the active flag.
+struct ArmArgs { long long n[kMaxBatch]; };
+__global__ void k_arm(WorkTab wt, ArmArgs aa) {
+    const int i = threadIdx.x;
+    if (i >= wt.n) return;
+    ProbDev *P = wt.prob[i];
+    P->steps_left = aa.n[i];
+    P->active = (aa.n[i] > 0 && P->err == 0 && P->dt > 0.0 &&
+                 (P->t_end <= 0.0 || P->t < P->t_end)) ? 1 : 0;
+}
+
+// ------------------------------------------------------------------ init --
+// Key and rank of every particle of the unsorted input (held in parity 1).
+template <int DIM, typename R>
+__global__ __launch_bounds__(kBlock) void k_init_keys(ProbDev *P) {
+    const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= P->np) return;
+    R x[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[1][PF_X + a])[k];
+    int c[3];
+    cell_of<DIM, R>(P, x, c);
+    const uint32_t nk = cell_key<DIM>(P, c);
+    P->key[k] = nk;
+    P->rank[k] = atomicAdd(&P->count[nk], 1u);
+}
+
+// Scatter parity 1 -> parity 0 in key order.
+template <int DIM, typename R>
+__global__ __launch_bounds__(kBlock) void k_init_permute(ProbDev *P) {
+    const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= P->np) return;
+    const uint32_t slot = P->offs[0][P->key[k]] + P->rank[k];
+    for (int f = 0; f < PF_N; ++f) {
+        if (!P->part[1][f]) continue;
+        ((R *)P->part[0][f])[slot] = ((const R *)P->part[1][f])[k];
+    }
+    P->pid[0][slot] = P->pid[1][k];
+}
+
+// Initial per-tile maxima and sums (parity 0, sorted): reuses the partials.
+template <int DIM, int SHAPE, typename R>
+__global__ __launch_bounds__(kBlock) void k_init_stats(ProbDev *P) {
+    using G = Geo<DIM, SHAPE>;
+    __shared__ double red[kBlock];
+    const int t = blockIdx.x;
+    const uint32_t pbeg = P->offs[0][(uint32_t)t * G::CELLS], pend = P->offs[0][(uint32_t)(t + 1) * G::CELLS];
+    double vmax = 0, cmax = 0, s[6] = {0, 0, 0, 0, 0, 0};
+    const R gam = (R)P->gamma;
+    for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
+        double v2 = 0;
+        const R M = ((const R *)P->part[0][PF_M])[k];
+        for (int a = 0; a < DIM; ++a) {
+            const R va = ((const R *)P->part[0][PF_V + a])[k];
+            v2 += (double)va * (double)va;
+            s[1 + a] += (double)M * (double)va;
+        }
+        const R rho = ((const R *)P->part[0][PF_RHO])[k];
+        const R e = ((const R *)P->part[0][PF_E])[k];
+        vmax = fmax(vmax, sqrt(v2));
+        cmax = fmax(cmax, (double)sound(gam, rho, eos_p(gam, rho, e)));
+        s[0] += (double)M;
+        s[4] += (double)M * (double)e;
+        s[5] += 0.5 * (double)M * v2;
+    }
+    double *pt = P->partials + (long long)t * PT_N;
+    const double r0 = block_reduce_max(vmax, red);
+    const double r1 = block_reduce_max(cmax, red);
+    double tot[6];
+    for (int c = 0; c < 6; ++c) tot[c] = block_reduce_sum(s[c], red);
+    if (threadIdx.x == 0) {
+        pt[PT_VMAX] = r0; pt[PT_CMAX] = r1; pt[PT_M] = tot[0];
+        pt[PT_MV] = tot[1]; pt[PT_MV + 1] = tot[2]; pt[PT_MV + 2] = tot[3];
+        pt[PT_ME] = tot[4]; pt[PT_MK] = tot[5];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_finalize(ProbDev *P) {
+    finalize_problem(P, false);
+    if (threadIdx.x == 0) { P->active = 0; P->parity = 0; }
+}
+
+// ------------------------------------------------------------ diagnostics --
+// Grid snapshot as double (raw accumulators or after the conditions).
+template <int DIM, int PREC>
+__global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, double *out) {
+    using R = typename PrecT<PREC>::real;
+    using A = typename PrecT<PREC>::acc;
+    const long long node = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long NN = P->nnodes;
+    if (node >= NN) return;
+    const A *gA = (const A *)P->gA;
+    const A *gB = (const A *)P->gB;
+    const double qm = PrecT<PREC>::fixed ? P->q_m : 1.0, qp = PrecT<PREC>::fixed ? P->q_p : 1.0;
+    const double dtl = P->dt_last > 0 ? P->dt_last : 1.0;
+    const uint8_t fl = P->nflag[node];
+    const double m = (double)gA[node] * qm;
+    double u[3] = {0, 0, 0};
+    switch (which) {
+    case 0: out[node] = m; return;
+    case 6: out[node] = (double)fl; return;
+    case 1: for (int a = 0; a < DIM; ++a) out[a * NN + node] = (double)gA[(1 + a) * NN + node] * qp; return;
+    case 2: for (int a = 0; a < DIM; ++a) out[a * NN + node] = (double)gA[(1 + DIM + a) * NN + node] * qp / dtl; return;
+    default: break;
+    }
+    // conditions applied in the state precision, as in the sweeps
+    uint32_t flags = 0;
+    R mr = from_acc<PREC>(gA[node], P->q_m, flags);
+    R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) {
+        if (which == 4) p[a] = from_acc<PREC>(gB[a * NN + node], P->q_p, flags);
+        else p[a] = from_acc<PREC>(gA[(1 + a) * NN + node], P->q_p, flags);
+        I[a] = from_acc<PREC>(gA[(1 + DIM + a) * NN + node], P->q_p, flags);
+    }
+    if (fl) { node_bc<DIM, R>(P, fl, node, mr, p, false); node_bc<DIM, R>(P, fl, node, mr, I, true); }
+    for (int a = 0; a < DIM; ++a) {
+        if (which == 3) u[a] = (double)(p[a] + I[a]);
+        else if (which == 4) u[a] = (double)p[a];
+        else u[a] = (double)I[a] / dtl;
+        out[a * NN + node] = u[a];
+    }
+}
+
+// ------------------------------------------------------------- launchers --
+static inline dim3 grid1(int n) { return dim3((unsigned)n); }
+
+// One sweep of the step (part 0..7 in launch order).
+template <int DIM, int SHAPE, int PREC>
+void launch_part_t(int part, const WorkTab &tiles, const WorkTab &zero, const WorkTab &chunks,
+                   const WorkTab &single, hipStream_t s) {
+    switch (part) {
+    case 0: hipLaunchKernelGGL(k_zero, grid1(zero.start[zero.n]), dim3(kBlock), 0, s, zero); break;
+    case 1: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
+    case 2: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
+    case 3: hipLaunchKernelGGL(k_scan_a, grid1(chunks.start[chunks.n]), dim3(kBlock), 0, s, chunks); break;
+    case 4: hipLaunchKernelGGL(k_scan_b, grid1(single.start[single.n]), dim3(kBlock), 0, s, single); break;
+    case 5: hipLaunchKernelGGL(k_scan_c, grid1(chunks.start[chunks.n]), dim3(kBlock), 0, s, chunks); break;
+    case 6: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
+    default: hipLaunchKernelGGL(k_finalize, grid1(single.start[single.n]), dim3(kBlock), 0, s, single); break;
+    }
+}
+
+template <int DIM, int SHAPE, int PREC>
+void launch_step_t(const WorkTab &tiles, const WorkTab &zero, const WorkTab &chunks,
+                   const WorkTab &single, hipStream_t s) {
+    for (int part = 0; part < kSweeps; ++part) launch_part_t<DIM, SHAPE, PREC>(part, tiles, zero, chunks, single, s);
+}
+
+template <int DIM, int SHAPE, int PREC>
+void launch_init_t(ProbDev *dP, const ProbDev &h, hipStream_t s) {
+    using R = typename PrecT<PREC>::real;
+    WorkTab one{};
+    one.prob[0] = dP; one.start[0] = 0; one.start[1] = 1; one.n = 1;
+    const unsigned nb = (unsigned)((h.np + kBlock - 1) / kBlock);
+    if (nb) hipLaunchKernelGGL((k_init_keys<DIM, R>), dim3(nb), dim3(kBlock), 0, s, dP);
+    WorkTab ch{};
+    ch.prob[0] = dP; ch.start[0] = 0; ch.start[1] = h.nchunks; ch.n = 1;
+    // the scan writes offs[parity ^ 1] = offs[0] while parity is 1 and active is 1
+    hipLaunchKernelGGL(k_scan_a, dim3(h.nchunks), dim3(kBlock), 0, s, ch);
+    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kBlock), 0, s, one);
+    hipLaunchKernelGGL(k_scan_c, dim3(h.nchunks), dim3(kBlock), 0, s, ch);
+    if (nb) hipLaunchKernelGGL((k_init_permute<DIM, R>), dim3(nb), dim3(kBlock), 0, s, dP);
+    hipLaunchKernelGGL((k_init_stats<DIM, SHAPE, R>), dim3(h.ntiles), dim3(kBlock), 0, s, dP);
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(kBlock), 0, s, dP);
+}
+
+template <int DIM, int PREC>
+void launch_grid_diag_t(ProbDev *dP, const ProbDev &h, int which, double *out, hipStream_t s) {
+    const unsigned nb = (unsigned)((h.nnodes + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_grid_diag<DIM, PREC>), dim3(nb), dim3(kBlock), 0, s, dP, which, out);
+}
+
+// Runtime dispatch over the instantiated variants.
+#define MPM_DISPATCH(DIMV, SHAPEV, PRECV, CALL)                                   \
+    do {                                                                          \
+        if ((DIMV) == 2 && (SHAPEV) == S_B2) {                                    \
+            switch (PRECV) {                                                      \
+            case P_FP64: CALL(2, S_B2, P_FP64); break;                            \
+            case P_F32_A64: CALL(2, S_B2, P_F32_A64); break;                      \
+            case P_F32_A32: CALL(2, S_B2, P_F32_A32); break;                      \
+            default: CALL(2, S_B2, P_F32_FIX); break;                             \
+            }                                                                     \
+        } else if ((DIMV) == 3 && (SHAPEV) == S_B2) {                             \
+            switch (PRECV) {                                                      \
+            case P_FP64: CALL(3, S_B2, P_FP64); break;                            \
+            case P_F32_A64: CALL(3, S_B2, P_F32_A64); break;                      \
+            case P_F32_A32: CALL(3, S_B2, P_F32_A32); break;                      \
+            default: CALL(3, S_B2, P_F32_FIX); break;                             \
+            }                                                                     \
+        } else if ((DIMV) == 2) {                                                 \
+            switch (PRECV) {                                                      \
+            case P_FP64: CALL(2, S_Q1, P_FP64); break;                            \
+            default: CALL(2, S_Q1, P_F32_FIX); break;                             \
+            }                                                                     \
+        } else {                                                                  \
+            switch (PRECV) {                                                      \
+            case P_FP64: CALL(3, S_Q1, P_FP64); break;                            \
+            default: CALL(3, S_Q1, P_F32_FIX); break;                             \
+            }                                                                     \
+        }                                                                         \
+    } while (0)
+
+void launch_step(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &zero,
+                 const WorkTab &chunks, const WorkTab &single, hipStream_t s) {
+#define CALL_STEP(D, S, Pr) launch_step_t<D, S, Pr>(tiles, zero, chunks, single, s)
+    MPM_DISPATCH(dim, shape, prec, CALL_STEP);
+#undef CALL_STEP
+}
+
+void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &zero,
+                 const WorkTab &chunks, const WorkTab &single, hipStream_t s) {
+#define CALL_PART(D, S, Pr) launch_part_t<D, S, Pr>(part, tiles, zero, chunks, single, s)
+    MPM_DISPATCH(dim, shape, prec, CALL_PART);
+#undef CALL_PART
+}
+
+void launch_init(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, hipStream_t s) {
+#define CALL_INIT(D, S, Pr) launch_init_t<D, S, Pr>(dP, h, s)
+    MPM_DISPATCH(dim, shape, prec, CALL_INIT);
+#undef CALL_INIT
+}
+
+void launch_grid_diag(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, int which,
+                      double *out, hipStream_t s) {
+#define CALL_DIAG(D, S, Pr) launch_grid_diag_t<D, Pr>(dP, h, which, out, s)
+    MPM_DISPATCH(dim, shape, prec, CALL_DIAG);
+#undef CALL_DIAG
+}
+
+void launch_arm(const WorkTab &single, const long long *n, hipStream_t s) {
+    ArmArgs aa{};
+    for (int i = 0; i < single.n; ++i) aa.n[i] = n[i];
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(kMaxBatch), 0, s, single, aa);
+}
+
+}  // namespace mpm

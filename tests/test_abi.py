@@ -1,0 +1,59 @@
+"""The C-ABI library loads on the CPU and exports every declared entry point.
+
+No compute call is made here (there is no GPU in the CPU suite)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2404_17057_amd import mpm as G
+from paper_2404_17057_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mpm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(G.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", G.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mpm_[a-z_]+)\b", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    L = ctypes.CDLL(G.LIB_PATH)
+    for f in declared_functions():
+        assert hasattr(L, f)
+
+
+def test_footprint_and_descriptor_checks_on_host():
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    pb = W.cylinder(nx=64, ny=32)
+    n64 = G.footprint(pb, G.FP64)
+    n32 = G.footprint(pb, G.FP32_FIX64)
+    assert n64 > n32 > pb.n_particles * 48
+    with pytest.raises(G.MPMError) as ei:
+        bad = W.Problem(**{**pb.__dict__})
+        bad.hi = (1.0, 0.7, 0.0)                 # cells not square
+        G.footprint(bad, G.FP64)
+    assert ei.value.code == G.E_ARG
+    assert G.lib().mpm_strerror(G.E_OVERFLOW).decode().startswith("fixed-point")
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(G, "_lib", None)
+    with pytest.raises(RuntimeError):
+        G.lib()
