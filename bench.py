@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain device copies of 256 MiB (reference for counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -216,6 +218,16 @@ def main():
         "accuracy_vs_oracle": accuracy,
         "kernel_source_hash": src_hash,
     }
+    if args.calibrate_copy:
+        # 256 MiB read + 256 MiB written per copy: the reference dispatch that
+        # scales FETCH_SIZE / WRITE_SIZE readings to bytes.
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 256 << 20
     print(json.dumps(line), flush=True)
 
 
