@@ -39,7 +39,7 @@ struct Layout {
     long long ncells_pad, nnodes, np;
     size_t real_sz, acc_sz;
     // byte offsets
-    size_t off_prob, off_part[2][PF_N], off_pid[2], off_key, off_rank;
+    size_t off_prob, off_part[2][PF_N], off_pid[2], off_key, off_rank, off_basetab;
     size_t off_gA, off_gB, off_count, off_zero_end, off_offs[2], off_blocksum, off_nflag, off_nrm,
         off_partials, total;
     int has_obstacle;
@@ -112,6 +112,12 @@ Layout make_layout(const mpm_desc *d) {
     }
     L.off_key = o; o = align_up(o + (size_t)L.np * 4);
     L.off_rank = o; o = align_up(o + (size_t)L.np * 4);
+    {
+        // per tile: one u32 per cell of its destination footprint (tile + 1 cell)
+        const size_t nd = d->dim == 2 ? (size_t)(Tile<2>::X + 2) * (Tile<2>::Y + 2)
+                                      : (size_t)(Tile<3>::X + 2) * (Tile<3>::Y + 2) * (Tile<3>::Z + 2);
+        L.off_basetab = o; o = align_up(o + (size_t)L.ntiles * nd * 4);
+    }
     L.off_gA = o; o = align_up(o + (size_t)(1 + 2 * d->dim) * L.nnodes * L.acc_sz);
     L.off_gB = o; o = align_up(o + (size_t)d->dim * L.nnodes * L.acc_sz);
     L.off_count = o; o = align_up(o + (size_t)L.ncells_pad * 4);
@@ -172,6 +178,7 @@ int read_dynamic(mpm_handle *h, ProbDev *out, hipStream_t s) {
 }
 
 int err_code(uint32_t err) {
+    if (err & ERR_INTERNAL) return MPM_E_STATE;
     if (err & ERR_OVERFLOW) return MPM_E_OVERFLOW;
     if (err & (ERR_NONPHYS | ERR_NONFINITE)) return MPM_E_NONPHYSICAL;
     return MPM_OK;
@@ -294,6 +301,7 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
     }
     P.key = (uint32_t *)(H->ws + L.off_key);
     P.rank = (uint32_t *)(H->ws + L.off_rank);
+    P.basetab = (uint32_t *)(H->ws + L.off_basetab);
     P.count = (uint32_t *)(H->ws + L.off_count);
     P.blocksum = (uint32_t *)(H->ws + L.off_blocksum);
     P.gA = H->ws + L.off_gA;

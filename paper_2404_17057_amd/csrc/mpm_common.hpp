@@ -15,11 +15,16 @@ namespace mpm {
 // -------------------------------------------------------------- precision --
 enum Prec { P_FP64 = 0, P_F32_A64 = 1, P_F32_A32 = 2, P_F32_FIX = 3 };
 
+// real: particle state and node arithmetic; acc: global grid accumulators;
+// lacc: per-lane and LDS partial sums.  In the fixed-point precision every
+// contribution is rounded to a whole number of quanta before it is added, so
+// the partial sums are integers held exactly in FP64 (|sum| < 2^53) and the
+// global accumulators are int64.
 template <int PREC> struct PrecT;
-template <> struct PrecT<P_FP64>    { using real = double; using acc = double;    static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_A64> { using real = float;  using acc = double;    static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_A32> { using real = float;  using acc = float;     static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_FIX> { using real = float;  using acc = long long; static constexpr bool fixed = true;  };
+template <> struct PrecT<P_FP64>    { using real = double; using acc = double;    using lacc = double; static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_A64> { using real = float;  using acc = double;    using lacc = double; static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_A32> { using real = float;  using acc = float;     using lacc = float;  static constexpr bool fixed = false; };
+template <> struct PrecT<P_F32_FIX> { using real = float;  using acc = long long; using lacc = double; static constexpr bool fixed = true;  };
 
 // ------------------------------------------------------------- constants --
 enum Shape { S_Q1 = 1, S_B2 = 2 };
@@ -29,7 +34,7 @@ enum Face { F_WALL = 0, F_INFLOW = 1, F_OUTFLOW = 2 };
 enum : uint8_t { NF_WALL_X = 1, NF_WALL_Y = 2, NF_WALL_Z = 4, NF_INFLOW = 8, NF_OBST = 16 };
 
 // Sticky error bits.
-enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_WALL = 8u };
+enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_WALL = 8u, ERR_INTERNAL = 16u };
 
 // Diagnostic counters (u64).
 enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2, DG_WIDE = 3 };
@@ -74,7 +79,9 @@ struct ProbDev {
     // ---- device pointers into the workspace
     void *part[2][PF_N];      // particle fields, per parity (real*)
     uint32_t *pid[2];         // particle ids, per parity
-    uint32_t *key, *rank;     // new cell key and rank within the cell (from S2)
+    uint32_t *key, *rank;     // new cell key and rank within the cell (from S2); a rank
+                              // with the top bit clear is relative to the tile's base
+    uint32_t *basetab;        // per tile: first rank of its particles in each footprint cell
     uint32_t *count;          // per-cell histogram of the new keys
     uint32_t *offs[2];        // exclusive prefix of counts, per parity (+1 entry)
     uint32_t *blocksum;       // scan chunk sums

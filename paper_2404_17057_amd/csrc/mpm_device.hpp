@@ -92,30 +92,42 @@ __device__ __forceinline__ R art_visc(int form, R c0, R c1, R gamma, R h, R rho,
 }
 
 // -------------------------------------------------------- fixed point --
-// Scaled contribution -> int64, round to nearest even.  The common case fits
-// 32 bits (one v_cvt_i32_f32); wider values take the exact 64-bit path;
-// beyond 2^62 the overflow bit is raised.
-__device__ __forceinline__ long long to_fix(float y, uint32_t &flags) {
-    const float r = rintf(y);
-    if (fabsf(r) < 2147483648.0f) return (long long)(int)r;
-    if (!(fabsf(r) < 4.611686018427388e18f)) { flags |= ERR_OVERFLOW; return 0; }
-    flags |= 0x100u;                                // diagnostic: wide path used
-    return (long long)r;
+// One contribution, already scaled to quanta, as a partial-sum term: in the
+// fixed-point precision it is rounded to the nearest whole quantum (ties to
+// even) first, so every partial sum is an integer and exact in FP64.
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::lacc to_lacc(typename PrecT<PREC>::real y) {
+    if constexpr (PrecT<PREC>::fixed) return (double)rintf(y);
+    else return (typename PrecT<PREC>::lacc)y;
 }
 
+// Partial sum -> global accumulator word.  Fixed point: the integer-valued
+// double becomes an int64; beyond 2^50 quanta the overflow bit is raised
+// (node sums stay near 2^32 quanta per cell mass).
 template <int PREC>
-__device__ __forceinline__ typename PrecT<PREC>::acc to_acc(typename PrecT<PREC>::real y, uint32_t &flags) {
-    if constexpr (PrecT<PREC>::fixed) return to_fix(y, flags);
-    else return (typename PrecT<PREC>::acc)y;
+__device__ __forceinline__ typename PrecT<PREC>::acc lacc_to_acc(typename PrecT<PREC>::lacc v, uint32_t &flags) {
+    if constexpr (PrecT<PREC>::fixed) {
+        if (!(fabs(v) < 1125899906842624.0)) { flags |= ERR_OVERFLOW; return 0; }
+        return (long long)v;
+    } else {
+        return (typename PrecT<PREC>::acc)v;
+    }
+}
+
+// int64 -> double, exact for |a| < 2^53 (two 32-bit conversions).
+__device__ __forceinline__ double i64_to_f64(long long a) {
+    const int hi = (int)(a >> 32);
+    const unsigned lo = (unsigned)(a & 0xffffffffLL);
+    return fma((double)hi, 4294967296.0, (double)lo);
 }
 
 template <int PREC>
 __device__ __forceinline__ typename PrecT<PREC>::real from_acc(typename PrecT<PREC>::acc a, double q, uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     if constexpr (PrecT<PREC>::fixed) {
-        const long long lim = 4611686018427387904LL;        // 2^62
+        const long long lim = 1LL << 50;
         if (a >= lim || a <= -lim) flags |= ERR_OVERFLOW;
-        return (R)a * (R)q;                                 // q is a power of two
+        return (R)(i64_to_f64(a) * q);                       // q is a power of two
     } else {
         (void)q;
         return (R)a;

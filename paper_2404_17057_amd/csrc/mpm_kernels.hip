@@ -28,6 +28,8 @@
 
 namespace mpm {
 
+template <typename R> struct R3 { R v[3]; };
+
 // ------------------------------------------------------------------- zero --
 __global__ __launch_bounds__(kBlock) void k_zero(WorkTab wt) {
     const int pi = find_prob(wt, blockIdx.x);
@@ -61,127 +63,141 @@ __device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], in
     lc[0] = l % TX; lc[1] = (l / TX) % TY; lc[2] = DIM == 3 ? l / (TX * TY) : 0;
 }
 
+// Footprint flush of an LDS partial-sum tile to the global accumulators.
+// Nodes that only this tile's cells reach (local index W-1 .. T-1 on every
+// axis) are stored; the frame shared with neighbouring tiles is added with
+// one atomic per non-zero value (the frame was cleared by k_zero).
+template <int DIM, int SHAPE, int PREC, int NQ>
+__device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
+                                           const typename PrecT<PREC>::lacc *tile,
+                                           typename PrecT<PREC>::acc *g, uint32_t &flags) {
+    using G = Geo<DIM, SHAPE>;
+    using L = typename PrecT<PREC>::lacc;
+    const long long NN = P->nnodes;
+    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) {
+        const int q = i / G::TN, li = i - q * G::TN;
+        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
+        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
+        if (gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
+        const bool own = ix >= G::W - 1 && ix < G::TX && iy >= G::W - 1 && iy < G::TY &&
+                         (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
+        const L val = tile[i];
+        auto *dst = &g[q * NN + node_index(P, gx, gy, gz)];
+        if (own) *dst = lacc_to_acc<PREC>(val, flags);
+        else if (val != (L)0) glb_add(dst, lacc_to_acc<PREC>(val, flags));
+    }
+}
+
 // -------------------------------------------------------------------- S1 --
+// Per-particle factors of S1: x-axis products of the separable stencil sums
+// for mass, momentum and impulse (all in quanta in the fixed-point mode).
+template <int DIM, int SHAPE, typename R> struct S1Factors {
+    static constexpr int W = Geo<DIM, SHAPE>::W;
+    R mx[W], fx[W], gx[W], px[3][W];
+};
+
+template <int DIM, int SHAPE, int PREC>
+__device__ __forceinline__ void s1_factors(const ProbDev *P, int par, uint32_t k,
+                                           const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
+                                           S1Factors<DIM, SHAPE, typename PrecT<PREC>::real> &f) {
+    using R = typename PrecT<PREC>::real;
+    constexpr int W = Geo<DIM, SHAPE>::W;
+    const R gam = (R)P->gamma, h = (R)P->h;
+    const R M = ((const R *)P->part[par][PF_M])[k];
+    const R rho = ((const R *)P->part[par][PF_RHO])[k];
+    const R e = ((const R *)P->part[par][PF_E])[k];
+    R v[3] = {0, 0, 0}, D = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        v[a] = ((const R *)P->part[par][PF_V + a])[k];
+        D += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
+    }
+    const R p = eos_p(gam, rho, e);
+    const R q = art_visc(P->av_form, (R)P->c0, (R)P->c1, gam, h, rho, p, D);
+    const R sm = PrecT<PREC>::fixed ? (R)P->inv_q_m : (R)1;
+    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
+    // M, M v and the impulse dt (P+Q) (M/rho) / h (the 1/h turns d/ds into d/dx)
+    const R Ms = M * sm;
+    const R Fs = (R)P->dt * (p + q) * (M / rho) * (R)P->inv_h * sp;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        f.mx[j] = Ms * st.w[0][j];
+        f.fx[j] = Fs * st.dw[0][j];
+        f.gx[j] = Fs * st.w[0][j];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) f.px[a][j] = (M * v[a] * sp) * st.w[0][j];
+    }
+}
+
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
+    using L = typename PrecT<PREC>::lacc;
     using A = typename PrecT<PREC>::acc;
     constexpr int NQ = 1 + 2 * DIM;
     constexpr int W = G::W;
-    __shared__ A tile[NQ * G::TN];
+    __shared__ L tile[NQ * G::TN];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
     if (!P->active) return;
     const int t = blockIdx.x - wt.start[pi];
 
-    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) tile[i] = (A)0;
+    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) tile[i] = (L)0;
     __syncthreads();
 
     int c0[3], lc[3];
     tile_cell<DIM>(P, t, c0, lc);
-    int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
-    bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
+    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
+    const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
     const int par = P->parity;
     const uint32_t *off = P->offs[par];
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
-
-    const R *X[3], *V[3], *Gd[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        X[a] = (const R *)P->part[par][PF_X + a];
-        V[a] = (const R *)P->part[par][PF_V + a];
-        Gd[a] = (const R *)P->part[par][PF_G + a * DIM + a];
-    }
-    const R *Mp = (const R *)P->part[par][PF_M];
-    const R *RHOp = (const R *)P->part[par][PF_RHO];
-    const R *Ep = (const R *)P->part[par][PF_E];
-    const R gam = (R)P->gamma, c0v = (R)P->c0, c1v = (R)P->c1, h = (R)P->h, inv_h = (R)P->inv_h;
-    const R dt = (R)P->dt;
-    const R sm = PrecT<PREC>::fixed ? (R)P->inv_q_m : (R)1;
-    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
-    const int form = P->av_form;
     uint32_t flags = 0;
     unsigned long long mismatch = 0;
 
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
-        A acc[G::WP][NQ];
+        L acc[G::WP][NQ];
 #pragma unroll
         for (int s = 0; s < G::WP; ++s)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[s][q] = (A)0;
+            for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
 
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
-            R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+            R x[3] = {0, 0, 0};
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) { x[a] = X[a][k]; v[a] = V[a][k]; }
+            for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[par][PF_X + a])[k];
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(P, x, st);
-            const R M = Mp[k], rho = RHOp[k], e = Ep[k];
-            R D = 0;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) D += Gd[a][k];
-            const R p = eos_p(gam, rho, e);
-            const R q = art_visc(form, c0v, c1v, gam, h, rho, p, D);
-            const R Ms = M * sm;
-            R MVs[3];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) MVs[a] = M * v[a] * sp;
-            // impulse scale dt (P+Q) (M/rho) / h; the 1/h turns d/ds into d/dx
-            const R Fs = dt * (p + q) * (M / rho) * inv_h * sp;
-
-            bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (!own) {
-                // Cell changed between sort and use: add this particle's
-                // contributions straight to the global grid (slow path).
-                if (pass == 0) {
-                    ++mismatch;
-                    A *g = (A *)P->gA;
-                    const long long NN = P->nnodes;
-                    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-                        for (int jy = 0; jy < W; ++jy)
-                            for (int jx = 0; jx < W; ++jx) {
-                                const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
-                                const R w = st.w[0][jx] * st.w[1][jy] * wz;
-                                R gr[3];
-                                gr[0] = st.dw[0][jx] * st.w[1][jy] * wz;
-                                gr[1] = st.w[0][jx] * st.dw[1][jy] * wz;
-                                gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] : (R)0;
-                                const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy,
-                                                                  DIM == 3 ? st.c[2] + jz : 0);
-                                glb_add(&g[node], to_acc<PREC>(Ms * w, flags));
-                                for (int a = 0; a < DIM; ++a) {
-                                    glb_add(&g[(1 + a) * NN + node], to_acc<PREC>(MVs[a] * w, flags));
-                                    glb_add(&g[(1 + DIM + a) * NN + node], to_acc<PREC>(Fs * gr[a], flags));
-                                }
-                            }
-                }
+            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+            if (!own) {            // handled after the register sums (rare)
+                if (pass == 0) ++mismatch;
                 continue;
             }
+            S1Factors<DIM, SHAPE, R> f;
+            s1_factors<DIM, SHAPE, PREC>(P, par, k, st, f);
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
             const R dwz = DIM == 3 ? st.dw[2][pass] : (R)0;
 #pragma unroll
-            for (int jy = 0; jy < W; ++jy)
+            for (int jy = 0; jy < W; ++jy) {
+                const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
+                const R dyz = DIM == 3 ? st.dw[1][jy] * wz : st.dw[1][jy];
+                const R ydz = st.w[1][jy] * dwz;
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx) {
-                    const int s = jy * W + jx;
-                    const R wxy = st.w[0][jx] * st.w[1][jy];
-                    const R w = wxy * wz;
-                    acc[s][0] += to_acc<PREC>(Ms * w, flags);
-                    R gr[3];
-                    gr[0] = st.dw[0][jx] * st.w[1][jy] * wz;
-                    gr[1] = st.w[0][jx] * st.dw[1][jy] * wz;
-                    gr[2] = wxy * dwz;
+                    L *ac = acc[jy * W + jx];
+                    ac[0] += to_lacc<PREC>(f.mx[jx] * wyz);
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        acc[s][1 + a] += to_acc<PREC>(MVs[a] * w, flags);
-                        acc[s][1 + DIM + a] += to_acc<PREC>(Fs * gr[a], flags);
-                    }
+                    for (int a = 0; a < DIM; ++a) ac[1 + a] += to_lacc<PREC>(f.px[a][jx] * wyz);
+                    ac[1 + DIM] += to_lacc<PREC>(f.fx[jx] * wyz);
+                    ac[2 + DIM] += to_lacc<PREC>(f.gx[jx] * dyz);
+                    if constexpr (DIM == 3) ac[3 + DIM] += to_lacc<PREC>(f.gx[jx] * ydz);
                 }
+            }
         }
         if (end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
@@ -189,39 +205,62 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             for (int jy = 0; jy < W; ++jy)
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx) {
-                    const int s = jy * W + jx;
                     const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
-                        if (acc[s][q] != (A)0) lds_add(&tile[q * G::TN + li], acc[s][q]);
+                        if (acc[jy * W + jx][q] != (L)0) lds_add(&tile[q * G::TN + li], acc[jy * W + jx][q]);
+                }
+        }
+    }
+    if (mismatch) {
+        // Particles whose cell changed between sort and use: their
+        // contributions go straight to the global grid.
+        A *g = (A *)P->gA;
+        const long long NN = P->nnodes;
+#pragma unroll 1
+        for (uint32_t k = beg; k < end; ++k) {
+            R x[3] = {0, 0, 0};
+            for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[par][PF_X + a])[k];
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(P, x, st);
+            if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
+            S1Factors<DIM, SHAPE, R> f;
+            s1_factors<DIM, SHAPE, PREC>(P, par, k, st, f);
+#pragma unroll 1
+            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll 1
+                for (int jy = 0; jy < W; ++jy) {
+                    const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
+                    const R wyz = st.w[1][jy] * wz, dyz = st.dw[1][jy] * wz;
+                    const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
+                    for (int jx = 0; jx < W; ++jx) {
+                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
+                        glb_add(&g[node], lacc_to_acc<PREC>(to_lacc<PREC>(f.mx[jx] * wyz), flags));
+                        for (int a = 0; a < DIM; ++a)
+                            glb_add(&g[(1 + a) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.px[a][jx] * wyz), flags));
+                        glb_add(&g[(1 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.fx[jx] * wyz), flags));
+                        glb_add(&g[(2 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.gx[jx] * dyz), flags));
+                        if (DIM == 3)
+                            glb_add(&g[(3 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.gx[jx] * ydz), flags));
+                    }
                 }
         }
     }
     __syncthreads();
-
-    // Flush the footprint to the global grid.
-    A *g = (A *)P->gA;
-    const long long NN = P->nnodes;
-    for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) {
-        const A val = tile[i];
-        if (val == (A)0) continue;
-        const int q = i / G::TN, li = i - q * G::TN;
-        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
-        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
-        if (gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
-        glb_add(&g[q * NN + node_index(P, gx, gy, gz)], val);
-    }
+    flush_tile<DIM, SHAPE, PREC, NQ>(P, c0, tile, (A *)P->gA, flags);
     if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
-    if (flags & 0x100u) atomicAdd((unsigned long long *)&P->diag[DG_WIDE], 1ull);
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
 }
 
-// Stage the tile footprint of nodes: fields[f * TN + li].
+// Stage the tile footprint of nodes, interleaved per node:
+// lds[li * 2DIM + f]: f < DIM vstar, f >= DIM dvel (S2) or v2 (S3).
 template <int DIM, int SHAPE, int PREC, bool WITH_B>
 __device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
                                            typename PrecT<PREC>::real *lds, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
+    constexpr int NF = 2 * DIM;
+#pragma unroll 1
     for (int li = threadIdx.x; li < G::TN; li += kBlock) {
         const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
         const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
@@ -238,68 +277,144 @@ __device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            lds[a * G::TN + li] = vs[a];
-            lds[(DIM + a) * G::TN + li] = dv[a];
+            lds[li * NF + a] = vs[a];
+            lds[li * NF + DIM + a] = dv[a];
         }
     }
 }
 
-// G2P of two staged vector fields at one particle: out0 = sum w f0,
-// out1 = sum w f1 (f0 = fields 0..DIM-1, f1 = DIM..2DIM-1).  The node order
-// is fixed, so the same particle gives the same bits in every sweep.
+// Staged value f of node (l0 + j) of the footprint.
 template <int DIM, int SHAPE, typename R>
-__device__ __forceinline__ void g2p_two(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3],
-                                        R out0[3], R out1[3]) {
+__device__ __forceinline__ const R *node_ptr(const R *lds, const int l0[3], int jx, int jy, int jz) {
     using G = Geo<DIM, SHAPE>;
-    constexpr int W = G::W;
+    return lds + (((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx)) * (2 * DIM);
+}
+
+// G2P of the staged vstar (fields 0..DIM-1) at one particle, summed row by
+// row: vbar = sum_z,y w_z w_y (sum_x w_x vstar).  S2 and S3 both call this,
+// so the same particle gets the same bits in both sweeps.
+template <int DIM, int SHAPE, typename R>
+__device__ __forceinline__ void g2p_vstar(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3], R vbar[3]) {
+    constexpr int W = Geo<DIM, SHAPE>::W;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { out0[a] = 0; out1[a] = 0; }
+    for (int a = 0; a < 3; ++a) vbar[a] = 0;
 #pragma unroll
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll
-        for (int jy = 0; jy < W; ++jy)
+        for (int jy = 0; jy < W; ++jy) {
+            R row[3] = {0, 0, 0};
 #pragma unroll
             for (int jx = 0; jx < W; ++jx) {
-                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
-                const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
+                const R *nd = node_ptr<DIM, SHAPE, R>(lds, l0, jx, jy, jz);
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    out0[a] += w * lds[a * G::TN + li];
-                    out1[a] += w * lds[(DIM + a) * G::TN + li];
-                }
+                for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[a];
             }
+            const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) vbar[a] += wyz * row[a];
+        }
 }
 
-// Same sums read straight from the global grid (slow path for a particle
-// whose stencil leaves the staged footprint).
-template <int DIM, int SHAPE, int PREC, bool WITH_B>
-__device__ __forceinline__ void g2p_two_global(const ProbDev *P, const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
-                                               typename PrecT<PREC>::real out0[3], typename PrecT<PREC>::real out1[3],
-                                               uint32_t &flags) {
+// The same G2P sums computed from the global grid, for a particle whose
+// stencil leaves the staged footprint: node values from the same staging
+// functions, summed in the same order.  Used only by the deferred loops.
+template <int DIM, int SHAPE, int PREC, bool SECOND_IS_B>
+__device__ __forceinline__ void g2p_global(const ProbDev *P, const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
+                                           typename PrecT<PREC>::real vbar[3], typename PrecT<PREC>::real other[3],
+                                           typename PrecT<PREC>::real Gm[9], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     constexpr int W = Geo<DIM, SHAPE>::W;
-    for (int a = 0; a < 3; ++a) { out0[a] = 0; out1[a] = 0; }
+    const R inv_h = (R)P->inv_h;
+    for (int a = 0; a < 3; ++a) { vbar[a] = 0; other[a] = 0; }
+    for (int c = 0; c < 9; ++c) Gm[c] = 0;
+#pragma unroll 1
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-        for (int jy = 0; jy < W; ++jy)
+#pragma unroll 1
+        for (int jy = 0; jy < W; ++jy) {
+            R row[3] = {0, 0, 0}, row2[3] = {0, 0, 0}, sx[3] = {0, 0, 0};
             for (int jx = 0; jx < W; ++jx) {
-                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
                 const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
-                R f0[3], f1[3], d2[3];
-                if constexpr (WITH_B) { stage_A<DIM, PREC>(P, node, f0, d2, flags); stage_B<DIM, PREC>(P, node, f1, flags); }
-                else stage_A<DIM, PREC>(P, node, f0, f1, flags);
-                for (int a = 0; a < DIM; ++a) { out0[a] += w * f0[a]; out1[a] += w * f1[a]; }
+                R vs[3], f1[3];
+                if constexpr (SECOND_IS_B) { R d[3]; stage_A<DIM, PREC>(P, node, vs, d, flags); stage_B<DIM, PREC>(P, node, f1, flags); }
+                else stage_A<DIM, PREC>(P, node, vs, f1, flags);
+                for (int a = 0; a < DIM; ++a) {
+                    row[a] += st.w[0][jx] * vs[a];
+                    row2[a] += st.w[0][jx] * f1[a];
+                    sx[a] += st.dw[0][jx] * f1[a];
+                }
             }
+            const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+            const R dyz = DIM == 3 ? st.dw[1][jy] * st.w[2][jz] : st.dw[1][jy];
+            const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
+            for (int a = 0; a < DIM; ++a) {
+                vbar[a] += wyz * row[a];
+                other[a] += wyz * row2[a];
+                Gm[a * DIM + 0] += wyz * sx[a];
+                Gm[a * DIM + 1] += dyz * row2[a];
+                if (DIM == 3) Gm[a * DIM + 2] += ydz * row2[a];
+            }
+        }
+    for (int c = 0; c < DIM * DIM; ++c) Gm[c] *= inv_h;
 }
 
+// Local index of a cell in the tile's destination footprint (cells c0-1 ..
+// c0+T per axis), or -1 when the cell lies outside it.
+template <int DIM>
+__device__ __forceinline__ int dest_local(const int c0[3], const int cn[3]) {
+    constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
+    const int lx = cn[0] - c0[0] + 1, ly = cn[1] - c0[1] + 1, lz = DIM == 3 ? cn[2] - c0[2] + 1 : 0;
+    if (lx < 0 || lx >= TX + 2 || ly < 0 || ly >= TY + 2 || (DIM == 3 && (lz < 0 || lz >= TZ + 2))) return -1;
+    return (lz * (TY + 2) + ly) * (TX + 2) + lx;
+}
+template <int DIM> struct DestFoot {
+    static constexpr int N = (Tile<DIM>::X + 2) * (Tile<DIM>::Y + 2) * (DIM == 3 ? Tile<DIM>::Z + 2 : 1);
+};
+
+// Cell triple of a tile-major key.
+template <int DIM>
+__device__ __forceinline__ void key_cell(const ProbDev *P, uint32_t key, int c[3]) {
+    constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
+    const uint32_t tile = key / Tile<DIM>::CELLS, l = key % Tile<DIM>::CELLS;
+    const int tx = (int)(tile % (uint32_t)P->ntile[0]);
+    const int ty = (int)((tile / (uint32_t)P->ntile[0]) % (uint32_t)P->ntile[1]);
+    const int tz = DIM == 3 ? (int)(tile / (uint32_t)(P->ntile[0] * P->ntile[1])) : 0;
+    c[0] = tx * TX + (int)(l % TX);
+    c[1] = ty * TY + (int)((l / TX) % TY);
+    c[2] = DIM == 3 ? tz * TZ + (int)(l / (TX * TY)) : 0;
+}
+
+constexpr uint32_t kRankGlobal = 0x80000000u;
+
 // -------------------------------------------------------------------- S2 --
+// New position of a particle -> its new cell key, and its rank within the
+// cell: from the tile's LDS histogram when the cell lies in the tile's
+// destination footprint (made global by one atomic per cell at the end),
+// else straight from the global histogram (flagged).
+template <int DIM, typename R>
+__device__ __forceinline__ void s2_key_rank(const ProbDev *P, uint32_t k, const R x[3], const R vbar[3],
+                                            R dt, uint32_t id, const int c0[3], uint32_t *hist) {
+    R xn[3] = {x[0], x[1], x[2]};
+    advect<DIM, R>(P, xn, vbar, dt, id);
+    int cn[3];
+    cell_of<DIM, R>(P, xn, cn);
+    const uint32_t nk = cell_key<DIM>(P, cn);
+    P->key[k] = nk;
+    const int dl = dest_local<DIM>(c0, cn);
+    P->rank[k] = dl >= 0 ? atomicAdd(&hist[dl], 1u) : (atomicAdd(&P->count[nk], 1u) | kRankGlobal);
+}
+
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
+    using L = typename PrecT<PREC>::lacc;
     using A = typename PrecT<PREC>::acc;
     constexpr int W = G::W;
-    __shared__ R stage[2 * DIM * G::TN];
-    __shared__ A tile[DIM * G::TN];
+    constexpr int NF = 2 * DIM;
+    constexpr int ND = DestFoot<DIM>::N;
+    __shared__ R stage[NF * G::TN];
+    __shared__ L tile[DIM * G::TN];
+    __shared__ uint32_t hist[ND];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
@@ -309,7 +424,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     tile_cell<DIM>(P, t, c0, lc);
     uint32_t flags = 0;
 
-    for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (A)0;
+    for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (L)0;
+    for (int i = threadIdx.x; i < ND; i += kBlock) hist[i] = 0;
     stage_tile<DIM, SHAPE, PREC, false>(P, c0, stage, flags);
     __syncthreads();
 
@@ -319,13 +435,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const uint32_t *off = P->offs[par];
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
-
-    R *X[3], *V[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        X[a] = (R *)P->part[par][PF_X + a];
-        V[a] = (R *)P->part[par][PF_V + a];
-    }
     const R *Mp = (const R *)P->part[par][PF_M];
     const uint32_t *ids = P->pid[par];
     const R dt = (R)P->dt;
@@ -334,63 +443,70 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
-        A acc[G::WP][DIM];
+        L acc[G::WP][DIM];
 #pragma unroll
         for (int s = 0; s < G::WP; ++s)
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) acc[s][a] = (A)0;
+            for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
 
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) { x[a] = X[a][k]; v[a] = V[a][k]; }
+            for (int a = 0; a < DIM; ++a) {
+                x[a] = ((const R *)P->part[par][PF_X + a])[k];
+                v[a] = ((const R *)P->part[par][PF_V + a])[k];
+            }
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(P, x, st);
-            const R M = Mp[k];
             const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (pass == 0) {
-                R vbar[3], dv[3];
-                if (own) g2p_two<DIM, SHAPE, R>(stage, st, lc, vbar, dv);
-                else { ++mismatch; g2p_two_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, flags); }
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) { v[a] = v[a] + dv[a]; V[a][k] = v[a]; }
-                // New position (not stored: the update sweep recomputes it
-                // from the same staged values) -> new cell key and rank.
-                R xn[3] = {x[0], x[1], x[2]};
-                advect<DIM, R>(P, xn, vbar, dt, ids[k]);
-                int cn[3];
-                cell_of<DIM, R>(P, xn, cn);
-                const uint32_t nk = cell_key<DIM>(P, cn);
-                P->key[k] = nk;
-                P->rank[k] = atomicAdd(&P->count[nk], 1u);
-            }
-            const R Ms = M * sp;
-            if (!own) {
-                if (pass == 0) {
-                    A *g = (A *)P->gB;
-                    const long long NN = P->nnodes;
-                    for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-                        for (int jy = 0; jy < W; ++jy)
-                            for (int jx = 0; jx < W; ++jx) {
-                                const R w = st.w[0][jx] * st.w[1][jy] * (DIM == 3 ? st.w[2][jz] : (R)1);
-                                const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy,
-                                                                  DIM == 3 ? st.c[2] + jz : 0);
-                                for (int a = 0; a < DIM; ++a)
-                                    glb_add(&g[a * NN + node], to_acc<PREC>(Ms * v[a] * w, flags));
-                            }
-                }
+            if (!own) {            // handled after the register sums (rare)
+                if (pass == 0) ++mismatch;
                 continue;
             }
+            if (pass == 0) {
+                // G2P of vstar and of the velocity increment, row by row
+                R vbar[3], dv[3];
+                g2p_vstar<DIM, SHAPE, R>(stage, st, lc, vbar);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dv[a] = 0;
+#pragma unroll
+                for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll
+                    for (int jy = 0; jy < W; ++jy) {
+                        R row[3] = {0, 0, 0};
+#pragma unroll
+                        for (int jx = 0; jx < W; ++jx) {
+                            const R *nd = node_ptr<DIM, SHAPE, R>(stage, lc, jx, jy, jz);
+#pragma unroll
+                            for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[DIM + a];
+                        }
+                        const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) dv[a] += wyz * row[a];
+                    }
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    v[a] = v[a] + dv[a];
+                    ((R *)P->part[par][PF_V + a])[k] = v[a];
+                }
+                s2_key_rank<DIM, R>(P, k, x, vbar, dt, ids[k], c0, hist);
+            }
+            const R M = Mp[k];
+            R px[3][W];
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) px[a][j] = (M * v[a] * sp) * st.w[0][j];
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
 #pragma unroll
-            for (int jy = 0; jy < W; ++jy)
+            for (int jy = 0; jy < W; ++jy) {
+                const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
 #pragma unroll
-                for (int jx = 0; jx < W; ++jx) {
-                    const R w = st.w[0][jx] * st.w[1][jy] * wz;
+                for (int jx = 0; jx < W; ++jx)
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_acc<PREC>(Ms * v[a] * w, flags);
-                }
+                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_lacc<PREC>(px[a][jx] * wyz);
+            }
         }
         if (end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
@@ -401,22 +517,57 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                     const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
                     for (int a = 0; a < DIM; ++a)
-                        if (acc[jy * W + jx][a] != (A)0) lds_add(&tile[a * G::TN + li], acc[jy * W + jx][a]);
+                        if (acc[jy * W + jx][a] != (L)0) lds_add(&tile[a * G::TN + li], acc[jy * W + jx][a]);
                 }
         }
     }
+    if (mismatch) {
+        // Particles whose cell changed between sort and use: G2P from the
+        // global grid, P2G straight to the global grid.
+        A *g = (A *)P->gB;
+        const long long NN = P->nnodes;
+#pragma unroll 1
+        for (uint32_t k = beg; k < end; ++k) {
+            R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+            for (int a = 0; a < DIM; ++a) {
+                x[a] = ((const R *)P->part[par][PF_X + a])[k];
+                v[a] = ((const R *)P->part[par][PF_V + a])[k];
+            }
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(P, x, st);
+            if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
+            R vbar[3], dv[3], Gd[9];
+            g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
+            for (int a = 0; a < DIM; ++a) {
+                v[a] = v[a] + dv[a];
+                ((R *)P->part[par][PF_V + a])[k] = v[a];
+            }
+            s2_key_rank<DIM, R>(P, k, x, vbar, dt, ids[k], c0, hist);
+            const R M = Mp[k];
+#pragma unroll 1
+            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll 1
+                for (int jy = 0; jy < W; ++jy)
+                    for (int jx = 0; jx < W; ++jx) {
+                        const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
+                        for (int a = 0; a < DIM; ++a)
+                            glb_add(&g[a * NN + node],
+                                    lacc_to_acc<PREC>(to_lacc<PREC>((M * v[a] * sp) * st.w[0][jx] * wyz), flags));
+                    }
+        }
+    }
     __syncthreads();
-
-    A *g = (A *)P->gB;
-    const long long NN = P->nnodes;
-    for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) {
-        const A val = tile[i];
-        if (val == (A)0) continue;
-        const int q = i / G::TN, li = i - q * G::TN;
-        const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
-        const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
-        if (gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
-        glb_add(&g[q * NN + node_index(P, gx, gy, gz)], val);
+    flush_tile<DIM, SHAPE, PREC, DIM>(P, c0, tile, (A *)P->gB, flags);
+    // One global histogram atomic per destination cell of this tile: the
+    // tile's particles of that cell get the ranks base .. base + hist - 1.
+    uint32_t *bt = P->basetab + (long long)t * ND;
+    for (int i = threadIdx.x; i < ND; i += kBlock) {
+        const uint32_t cnt = hist[i];
+        if (!cnt) continue;
+        const int lx = i % (G::TX + 2), ly = (i / (G::TX + 2)) % (G::TY + 2), lz = i / ((G::TX + 2) * (G::TY + 2));
+        const int cn[3] = {c0[0] + lx - 1, c0[1] + ly - 1, DIM == 3 ? c0[2] + lz - 1 : 0};
+        bt[i] = atomicAdd(&P->count[cell_key<DIM>(P, cn)], cnt);
     }
     if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
@@ -527,12 +678,158 @@ __device__ __forceinline__ T block_reduce_max(T v, T *sh) {
     return r;
 }
 
+// Running per-tile results of S3.
+struct S3Sums {
+    double vmax2, cmax2, M, MV[3], ME, MK;
+    unsigned long long mis, rec, wall;
+};
+
+// The whole particle update of S3 for one particle whose old stencil is st:
+// G2PD / G2P (from the staged footprint, or from the global grid when
+// GLOBAL), energy and density update, move, recycling, scatter into the
+// next sorted order, CFL maxima and FP64 sums.
+template <int DIM, int SHAPE, int PREC, bool GLOBAL>
+__device__ __forceinline__ void s3_particle(ProbDev *P, uint32_t k, const R3<typename PrecT<PREC>::real> &xin,
+                                            const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
+                                            const int l0[3], const int c0[3],
+                                            const typename PrecT<PREC>::real *stage, const uint32_t *sbase,
+                                            S3Sums &sums, uint32_t &flags) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    constexpr int W = G::W;
+    const int par = P->parity, npar = par ^ 1;
+    const R dt = (R)P->dt;
+    const R gam = (R)P->gamma, h = (R)P->h, inv_h = (R)P->inv_h;
+
+    R x[3] = {xin.v[0], xin.v[1], xin.v[2]}, v[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v[a] = ((const R *)P->part[par][PF_V + a])[k];
+    R M = ((const R *)P->part[par][PF_M])[k];
+    const R rho = ((const R *)P->part[par][PF_RHO])[k];
+    const R e = ((const R *)P->part[par][PF_E])[k];
+    R Dprev = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) Dprev += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
+    const uint32_t id = P->pid[par][k];
+    const uint32_t nk = P->key[k], rk = P->rank[k];
+
+    R Gm[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Gm[c] = 0;
+    R vbar[3] = {0, 0, 0};
+    if constexpr (!GLOBAL) {
+        // G2PD of v2, summed row by row
+#pragma unroll
+        for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
+#pragma unroll
+            for (int jy = 0; jy < W; ++jy) {
+                R row2[3] = {0, 0, 0}, sx[3] = {0, 0, 0};
+#pragma unroll
+                for (int jx = 0; jx < W; ++jx) {
+                    const R *nd = node_ptr<DIM, SHAPE, R>(stage, l0, jx, jy, jz);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        row2[a] += st.w[0][jx] * nd[DIM + a];
+                        sx[a] += st.dw[0][jx] * nd[DIM + a];
+                    }
+                }
+                const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+                const R dyz = DIM == 3 ? st.dw[1][jy] * st.w[2][jz] : st.dw[1][jy];
+                const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    Gm[a * DIM + 0] += wyz * sx[a];
+                    Gm[a * DIM + 1] += dyz * row2[a];
+                    if (DIM == 3) Gm[a * DIM + 2] += ydz * row2[a];
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < DIM * DIM; ++c) Gm[c] *= inv_h;
+        g2p_vstar<DIM, SHAPE, R>(stage, st, l0, vbar);
+    } else {
+        R v2i[3];
+        g2p_global<DIM, SHAPE, PREC, true>(P, st, vbar, v2i, Gm, flags);
+    }
+
+    R D = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) D += Gm[a * DIM + a];
+    const R p = eos_p(gam, rho, e);
+    const R q = art_visc(P->av_form, (R)P->c0, (R)P->c1, gam, h, rho, p, Dprev);
+    const R J = (R)1 + dt * D;
+    if (!(J > (R)0)) flags |= ERR_NONPHYS;
+    // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.
+    const double en = (double)e - P->dt * ((double)p + (double)q) * (double)D / (double)rho;
+    R rhon = rho / J;
+    R En = (R)en;
+
+    const int mv = advect<DIM, R>(P, x, vbar, dt, id);
+    if (mv == 1) {
+        ++sums.rec;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) v[a] = (R)P->inflow_u[a];
+        rhon = (R)P->inflow_rho;
+        En = (R)P->inflow_e;
+        M = (R)P->recycle_mass;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Gm[c] = 0;
+    } else if (mv == 2) {
+        ++sums.wall;
+    }
+    if (!isfinite((double)En) || !isfinite((double)rhon)) flags |= ERR_NONFINITE;
+
+    // Slot in the next sorted order: the cell's offset plus the rank.
+    const uint32_t np = (uint32_t)P->np;
+    const uint32_t *noff = P->offs[npar];
+    uint32_t slot;
+    if (rk & kRankGlobal) {
+        slot = noff[nk] + (rk & ~kRankGlobal);
+    } else {
+        int cn[3];
+        key_cell<DIM>(P, nk, cn);
+        const int dl = dest_local<DIM>(c0, cn);
+        slot = dl >= 0 ? noff[nk] + sbase[dl] + rk : np;
+    }
+    if (slot >= np) {
+        flags |= ERR_INTERNAL;
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        ((R *)P->part[npar][PF_X + a])[slot] = x[a];
+        ((R *)P->part[npar][PF_V + a])[slot] = v[a];
+    }
+    ((R *)P->part[npar][PF_M])[slot] = M;
+    ((R *)P->part[npar][PF_RHO])[slot] = rhon;
+    ((R *)P->part[npar][PF_E])[slot] = En;
+#pragma unroll
+    for (int c = 0; c < DIM * DIM; ++c) ((R *)P->part[npar][PF_G + c])[slot] = Gm[c];
+    P->pid[npar][slot] = id;
+
+    // CFL maxima (squared) and FP64 sums of the new state
+    double v2 = 0, vb2 = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        v2 += (double)v[a] * (double)v[a];
+        vb2 += (double)vbar[a] * (double)vbar[a];
+        sums.MV[a] += (double)M * (double)v[a];
+    }
+    sums.vmax2 = fmax(sums.vmax2, fmax(v2, vb2));
+    const R pn = eos_p(gam, rhon, En);
+    sums.cmax2 = fmax(sums.cmax2, (double)(gam * pn / rhon));
+    sums.M += (double)M;
+    sums.ME += (double)M * (double)En;
+    sums.MK += 0.5 * (double)M * v2;
+}
+
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
-    constexpr int W = G::W;
-    __shared__ R stage[2 * DIM * G::TN];
+    constexpr int NF = 2 * DIM;
+    constexpr int ND = DestFoot<DIM>::N;
+    __shared__ R stage[NF * G::TN];
+    __shared__ uint32_t sbase[ND];
     __shared__ double red[kBlock];
 
     const int pi = find_prob(wt, blockIdx.x);
@@ -543,162 +840,63 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     tile_cell<DIM>(P, t, c0, lc);
     uint32_t flags = 0;
     stage_tile<DIM, SHAPE, PREC, true>(P, c0, stage, flags);
+    const uint32_t *bt = P->basetab + (long long)t * ND;
+    for (int i = threadIdx.x; i < ND; i += kBlock) sbase[i] = bt[i];
     __syncthreads();
 
-    const int par = P->parity, npar = par ^ 1;
+    const int par = P->parity;
     const uint32_t *off = P->offs[par];
-    const uint32_t *noff = P->offs[npar];
     const uint32_t pbeg = off[(uint32_t)t * G::CELLS], pend = off[(uint32_t)(t + 1) * G::CELLS];
-    const R dt = (R)P->dt;
-    const double dtd = P->dt;
-    const R gam = (R)P->gamma, c0v = (R)P->c0, c1v = (R)P->c1, h = (R)P->h, inv_h = (R)P->inv_h;
-    const int form = P->av_form;
+    S3Sums sums = {0, 0, 0, {0, 0, 0}, 0, 0, 0, 0, 0};
 
-    double vmax = 0, cmax = 0, sM = 0, sMV[3] = {0, 0, 0}, sME = 0, sMK = 0;
-    unsigned long long n_mis = 0, n_rec = 0, n_wall = 0;
-
+#pragma unroll 1
     for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
-        R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+        R3<R> x = {{0, 0, 0}};
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            x[a] = ((const R *)P->part[par][PF_X + a])[k];
-            v[a] = ((const R *)P->part[par][PF_V + a])[k];
-        }
-        R M = ((const R *)P->part[par][PF_M])[k];
-        const R rho = ((const R *)P->part[par][PF_RHO])[k];
-        const R e = ((const R *)P->part[par][PF_E])[k];
-        R Dprev = 0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) Dprev += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
-        const uint32_t id = P->pid[par][k];
-
+        for (int a = 0; a < DIM; ++a) x.v[a] = ((const R *)P->part[par][PF_X + a])[k];
         Stencil<DIM, SHAPE, R> st;
-        make_stencil<DIM, SHAPE, R>(P, x, st);
-        int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+        make_stencil<DIM, SHAPE, R>(P, x.v, st);
+        const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
         const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
                             (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
-
-        // G2PD of v2 (velocity gradient) and G2P of vstar (Vbar)
-        R Gm[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) Gm[c] = 0;
-        R vbar[3] = {0, 0, 0};
-        if (inside) {
-#pragma unroll
-            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-#pragma unroll
-                for (int jy = 0; jy < W; ++jy)
-#pragma unroll
-                    for (int jx = 0; jx < W; ++jx) {
-                        const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
-                        R gr[3];
-                        gr[0] = st.dw[0][jx] * st.w[1][jy] * wz * inv_h;
-                        gr[1] = st.w[0][jx] * st.dw[1][jy] * wz * inv_h;
-                        gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] * inv_h : (R)0;
-                        const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            const R va = stage[(DIM + a) * G::TN + li];
-#pragma unroll
-                            for (int b = 0; b < DIM; ++b) Gm[a * DIM + b] += va * gr[b];
-                        }
-                    }
-            R dummy[3];
-            g2p_two<DIM, SHAPE, R>(stage, st, l0, vbar, dummy);
-        } else {
-            ++n_mis;
-            for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-                for (int jy = 0; jy < W; ++jy)
-                    for (int jx = 0; jx < W; ++jx) {
-                        const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
-                        R gr[3];
-                        gr[0] = st.dw[0][jx] * st.w[1][jy] * wz * inv_h;
-                        gr[1] = st.w[0][jx] * st.dw[1][jy] * wz * inv_h;
-                        gr[2] = DIM == 3 ? st.w[0][jx] * st.w[1][jy] * st.dw[2][jz] * inv_h : (R)0;
-                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
-                        R v2n[3];
-                        stage_B<DIM, PREC>(P, node, v2n, flags);
-                        for (int a = 0; a < DIM; ++a)
-                            for (int b = 0; b < DIM; ++b) Gm[a * DIM + b] += v2n[a] * gr[b];
-                    }
-            R dummy[3];
-            g2p_two_global<DIM, SHAPE, PREC, false>(P, st, vbar, dummy, flags);
+        if (!inside) { ++sums.mis; continue; }       // handled below (rare)
+        s3_particle<DIM, SHAPE, PREC, false>(P, k, x, st, l0, c0, stage, sbase, sums, flags);
+    }
+    if (sums.mis) {
+#pragma unroll 1
+        for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
+            R3<R> x = {{0, 0, 0}};
+            for (int a = 0; a < DIM; ++a) x.v[a] = ((const R *)P->part[par][PF_X + a])[k];
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(P, x.v, st);
+            const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+            const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
+                                (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
+            if (inside) continue;
+            s3_particle<DIM, SHAPE, PREC, true>(P, k, x, st, l0, c0, stage, sbase, sums, flags);
         }
-
-        R D = 0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) D += Gm[a * DIM + a];
-        const R p = eos_p(gam, rho, e);
-        const R q = art_visc(form, c0v, c1v, gam, h, rho, p, Dprev);
-        const R J = (R)1 + dt * D;
-        if (!(J > (R)0)) flags |= ERR_NONPHYS;
-        // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.
-        double en = (double)e - dtd * ((double)p + (double)q) * (double)D / (double)rho;
-        R rhon = rho / J;
-        R En = (R)en;
-
-        const int mv = advect<DIM, R>(P, x, vbar, dt, id);
-        if (mv == 1) {
-            ++n_rec;
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) v[a] = (R)P->inflow_u[a];
-            rhon = (R)P->inflow_rho;
-            En = (R)P->inflow_e;
-            M = (R)P->recycle_mass;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) Gm[c] = 0;
-        } else if (mv == 2) {
-            ++n_wall;
-        }
-        if (!isfinite((double)En) || !isfinite((double)rhon)) flags |= ERR_NONFINITE;
-
-        const uint32_t slot = noff[P->key[k]] + P->rank[k];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            ((R *)P->part[npar][PF_X + a])[slot] = x[a];
-            ((R *)P->part[npar][PF_V + a])[slot] = v[a];
-        }
-        ((R *)P->part[npar][PF_M])[slot] = M;
-        ((R *)P->part[npar][PF_RHO])[slot] = rhon;
-        ((R *)P->part[npar][PF_E])[slot] = En;
-#pragma unroll
-        for (int c = 0; c < DIM * DIM; ++c) ((R *)P->part[npar][PF_G + c])[slot] = Gm[c];
-        P->pid[npar][slot] = id;
-
-        // CFL maxima and FP64 sums of the new state
-        double v2 = 0, vb2 = 0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            v2 += (double)v[a] * (double)v[a];
-            vb2 += (double)vbar[a] * (double)vbar[a];
-            sMV[a] += (double)M * (double)v[a];
-        }
-        vmax = fmax(vmax, fmax(sqrt(v2), sqrt(vb2)));
-        const R pn = eos_p(gam, rhon, En);
-        cmax = fmax(cmax, (double)sound(gam, rhon, pn));
-        sM += (double)M;
-        sME += (double)M * (double)En;
-        sMK += 0.5 * (double)M * v2;
     }
 
     double *pt = P->partials + (long long)t * PT_N;
-    const double r0 = block_reduce_max(vmax, red);
-    const double r1 = block_reduce_max(cmax, red);
-    const double r2 = block_reduce_sum(sM, red);
+    // squared maxima: one square root per tile instead of per particle
+    const double r0 = sqrt(block_reduce_max(sums.vmax2, red));
+    const double c2 = block_reduce_max(sums.cmax2, red);
+    const double r1 = c2 > 0.0 ? sqrt(c2) : 0.0;
+    const double r2 = block_reduce_sum(sums.M, red);
     double rv[3];
-    for (int a = 0; a < 3; ++a) rv[a] = block_reduce_sum(sMV[a], red);
-    const double r6 = block_reduce_sum(sME, red);
-    const double r7 = block_reduce_sum(sMK, red);
+    for (int a = 0; a < 3; ++a) rv[a] = block_reduce_sum(sums.MV[a], red);
+    const double r6 = block_reduce_sum(sums.ME, red);
+    const double r7 = block_reduce_sum(sums.MK, red);
     if (threadIdx.x == 0) {
         pt[PT_VMAX] = r0; pt[PT_CMAX] = r1; pt[PT_M] = r2;
         pt[PT_MV] = rv[0]; pt[PT_MV + 1] = rv[1]; pt[PT_MV + 2] = rv[2];
         pt[PT_ME] = r6; pt[PT_MK] = r7;
     }
-    if (flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW))
-        atomicOr((uint32_t *)&P->err, flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW));
-    if (n_mis) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], n_mis);
-    if (n_rec) atomicAdd((unsigned long long *)&P->diag[DG_RECYCLE], n_rec);
-    if (n_wall) atomicAdd((unsigned long long *)&P->diag[DG_WALL], n_wall);
+    const uint32_t errs = flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW | ERR_INTERNAL);
+    if (errs) atomicOr((uint32_t *)&P->err, errs);
+    if (sums.mis) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], sums.mis);
+    if (sums.rec) atomicAdd((unsigned long long *)&P->diag[DG_RECYCLE], sums.rec);
+    if (sums.wall) atomicAdd((unsigned long long *)&P->diag[DG_WALL], sums.wall);
 }
 
 // -------------------------------------------------------------- finalize --
@@ -779,6 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_init_permute(ProbDev *P) {
     const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (k >= P->np) return;
     const uint32_t slot = P->offs[0][P->key[k]] + P->rank[k];
+    if (slot >= (uint32_t)P->np) { atomicOr((uint32_t *)&P->err, ERR_INTERNAL); return; }
     for (int f = 0; f < PF_N; ++f) {
         if (!P->part[1][f]) continue;
         ((R *)P->part[0][f])[slot] = ((const R *)P->part[1][f])[k];
