@@ -37,18 +37,22 @@ def log(*a):
 def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     """Algorithmic bytes per launch of each sweep: every particle field and
     grid word the sweep must read or write, counted once (no halo re-reads,
-    no atomic retries, no cache effects)."""
+    no clearing of the next step's buffers, no atomic retries)."""
     d = pb.dim
     N = pb.n_particles
     r, a = real_sz, acc_sz
     nq = 1 + 2 * d
     return {
-        "clear": nnodes * (nq + d) * a + ncells * 4,
+        # X, V, M, rho, e, diag G in; m, p, dt f out; cell offsets in
         "p2g": N * (3 * d + 3) * r + ncells * 4 + nnodes * nq * a,
+        # X, V, M in; V, key, rank out; m, p, dt f, flags in; p2 out; offsets in
         "g2p_p2g": N * ((3 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
-        "scan_a": ncells * 4,
-        "scan_b": 0,
-        "scan_c": ncells * 8,
+        # tile totals in, tile bases out
+        "tilescan": (ncells // 256) * 8,
+        # cell counts in, offsets out
+        "cellscan": ncells * 8,
+        # X, V, M, rho, e, diag G, id, key, rank, offset in; X, V, M, rho, e,
+        # G, id out; m, p, dt f, p2, flags in
         "update": N * ((3 * d + 3) * r + 12 + (2 * d + 3 + d * d) * r + 4 + 4) + nnodes * ((1 + 3 * d) * a + 1),
         "finalize": 0,
     }
@@ -115,6 +119,66 @@ def run_sample_gpu(pb, precision, steps):
     return rho
 
 
+def ablation(args):
+    """Accumulation precision on the 512x256 cylinder, 4x4 particles per cell:
+    FP32 state with FP64 atomics, FP32 atomics or int64 fixed point (and
+    the plain FP64 path).  Per precision: two runs of `--ablation-steps`
+    steps compared bit for bit, the largest relative gap between the grid
+    mass and the particle mass seen every 10 steps, throughput, and the L1
+    density error against the oracle after `--ablation-oracle-steps`."""
+    import numpy as np
+    from paper_2404_17057_amd import mpm as G
+    from paper_2404_17057_amd import workloads as W
+    from oracle import oracle as O
+    pb = W.cylinder(nx=512, ny=256, per_axis=4, steps=args.ablation_steps)
+    M0 = float(pb.mass.sum())
+    o = O.Oracle(pb)
+    o.step(args.ablation_oracle_steps)
+    rho_o = o.particles(O.F_RHO)
+    o.close()
+    out = {"workload": f"cylinder_mach3_512x256_ppc16 ({pb.n_particles} particles)",
+           "steps": args.ablation_steps, "oracle_steps": args.ablation_oracle_steps, "modes": {}}
+    for name, prec in (("fp32_acc_f64", G.FP32_ACC_F64), ("fp32_acc_f32", G.FP32_ACC_F32),
+                       ("fp32_fix64", G.FP32_FIX64), ("fp64", G.FP64)):
+        rec = {}
+        s = G.Simulation(pb, prec)
+        s.step(args.ablation_oracle_steps)
+        rho = s.field(G.F_RHO)
+        rec["rel_l1_density_vs_oracle"] = float(np.abs(rho - rho_o).sum() / np.abs(rho_o).sum())
+        s.close()
+        finals = []
+        for run in range(2):
+            s = G.Simulation(pb, prec)
+            drift = 0.0
+            done = 0
+            t0 = time.perf_counter()
+            while done < args.ablation_steps:
+                k = min(10, args.ablation_steps - done)
+                s.step(k)
+                done += k
+                if run == 0:
+                    drift = max(drift, abs(float(s.grid(G.G_M).sum()) - M0) / M0)
+            if run == 1:
+                torch_sync()
+                rec["particle_steps_per_s_incl_readbacks"] = pb.n_particles * done / (time.perf_counter() - t0)
+            else:
+                rec["max_rel_mass_drift"] = drift
+            finals.append(s.read([G.F_X, G.F_RHO, G.F_V]))
+            rec["status"] = s.status()["rc"]
+            s.close()
+        rec["bitwise_reproducible"] = all(np.array_equal(finals[0][f], finals[1][f]) for f in finals[0])
+        rec["run_to_run_max_rel_density_diff"] = float(np.abs(finals[0][G.F_RHO] - finals[1][G.F_RHO]).max()
+                                                      / np.abs(finals[0][G.F_RHO]).max())
+        out["modes"][name] = rec
+        log(f"ablation {name}: {rec}")
+    return {"metric": "precision ablation (configs[3])", **out}
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +190,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the serving stream (Poisson, 200/s, seed 2404; 0 = skip)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="precision ablation on the 512x256 cylinder with 4x4 particles per cell "
+                         "(prints its own JSON line instead of the throughput line)")
+    ap.add_argument("--ablation-steps", type=int, default=1000)
+    ap.add_argument("--ablation-oracle-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of 256 MiB (reference for counter scaling)")
     args = ap.parse_args()
@@ -141,6 +212,9 @@ def main():
     from paper_2404_17057_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.ablation:
+        print(json.dumps(ablation(args)), flush=True)
+        return
     pb = W.cylinder(nx=args.nx, ny=args.nx // 2)
     N = pb.n_particles
     log(f"workload {pb.name}: {N} particles")
@@ -193,6 +267,20 @@ def main():
             accuracy["rel_l1_density_fp64"] = l1(run_sample_gpu(pb, G.FP64, args.cpu_steps))
         o.close()
 
+    serving = None
+    if args.serve_requests > 0:
+        from paper_2404_17057_amd import serving as S
+        specs = W.request_stream(n=args.serve_requests, rate=200.0, seed=2404)
+        cache = W.LatticeCache()
+        srv = S.Server(S.GPUBackend(G.FP32_FIX64), lambda sp: W.build_request(sp, cache),
+                       hbm_budget=64 << 30, max_slots=64, steps_per_launch=16)
+        done = srv.run(specs)
+        serving = S.summarize(done)
+        serving.update({"stream": f"{args.serve_requests} requests, Poisson 200/s, seed 2404",
+                        "precision": "fp32 state, int64 fixed-point P2G", "max_slots": 64,
+                        "steps_per_launch": 16})
+        log(f"serving: {serving}")
+
     line = {
         "metric": METRIC,
         "value": round(fix["value"], 1),
@@ -216,6 +304,7 @@ def main():
                                           "sweeps_ms": fp64["sweeps_ms"]},
         "sweeps_ms": sw,
         "accuracy_vs_oracle": accuracy,
+        "serving": serving,
         "kernel_source_hash": src_hash,
     }
     if args.calibrate_copy:

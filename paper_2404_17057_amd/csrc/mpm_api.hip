@@ -13,15 +13,13 @@
 #include "mpm_common.hpp"
 
 namespace mpm {
-int zero_blocks(const ProbDev &h);
-void launch_step(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &zero,
-                 const WorkTab &chunks, const WorkTab &single, hipStream_t s);
+void launch_step(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &single, hipStream_t s);
 void launch_init(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, hipStream_t s);
 void launch_grid_diag(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, int which,
                       double *out, hipStream_t s);
 void launch_arm(const WorkTab &single, const long long *n, hipStream_t s);
-void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &zero,
-                 const WorkTab &chunks, const WorkTab &single, hipStream_t s);
+void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &single,
+                 hipStream_t s);
 }  // namespace mpm
 
 using namespace mpm;
@@ -40,8 +38,8 @@ struct Layout {
     size_t real_sz, acc_sz;
     // byte offsets
     size_t off_prob, off_part[2][PF_N], off_pid[2], off_key, off_rank, off_basetab;
-    size_t off_gA, off_gB, off_count, off_zero_end, off_offs[2], off_blocksum, off_nflag, off_nrm,
-        off_partials, total;
+    size_t off_gA[2], off_gB[2], off_count, off_ttot, off_tbase, off_zero_end, off_offs[2], off_blocksum,
+        off_nflag, off_nrm, off_partials, total;
     int has_obstacle;
 };
 
@@ -118,10 +116,14 @@ Layout make_layout(const mpm_desc *d) {
                                       : (size_t)(Tile<3>::X + 2) * (Tile<3>::Y + 2) * (Tile<3>::Z + 2);
         L.off_basetab = o; o = align_up(o + (size_t)L.ntiles * nd * 4);
     }
-    L.off_gA = o; o = align_up(o + (size_t)(1 + 2 * d->dim) * L.nnodes * L.acc_sz);
-    L.off_gB = o; o = align_up(o + (size_t)d->dim * L.nnodes * L.acc_sz);
+    for (int p = 0; p < 2; ++p) {
+        L.off_gA[p] = o; o = align_up(o + (size_t)(1 + 2 * d->dim) * L.nnodes * L.acc_sz);
+        L.off_gB[p] = o; o = align_up(o + (size_t)d->dim * L.nnodes * L.acc_sz);
+    }
     L.off_count = o; o = align_up(o + (size_t)L.ncells_pad * 4);
+    L.off_ttot = o; o = align_up(o + (size_t)L.ntiles * 4);
     L.off_zero_end = o;
+    L.off_tbase = o; o = align_up(o + (size_t)(L.ntiles + 1) * 4);
     for (int p = 0; p < 2; ++p) { L.off_offs[p] = o; o = align_up(o + (size_t)(L.ncells_pad + 1) * 4); }
     L.off_blocksum = o; o = align_up(o + (size_t)L.nchunks * 4);
     L.off_nflag = o; o = align_up(o + (size_t)L.nnodes);
@@ -148,27 +150,24 @@ struct mpm_handle {
 
 namespace {
 
-void make_tables(mpm_handle *const *hs, int n, WorkTab &tiles, WorkTab &zero, WorkTab &chunks,
-                 WorkTab &single) {
-    tiles = WorkTab{}; zero = WorkTab{}; chunks = WorkTab{}; single = WorkTab{};
-    int bt = 0, bz = 0, bc = 0;
+void make_tables(mpm_handle *const *hs, int n, WorkTab &tiles, WorkTab &single) {
+    tiles = WorkTab{}; single = WorkTab{};
+    int bt = 0;
     for (int i = 0; i < n; ++i) {
         ProbDev *p = hs[i]->dev;
-        tiles.prob[i] = zero.prob[i] = chunks.prob[i] = single.prob[i] = p;
+        tiles.prob[i] = single.prob[i] = p;
         tiles.start[i] = bt; bt += hs[i]->host.ntiles;
-        zero.start[i] = bz; bz += zero_blocks(hs[i]->host);
-        chunks.start[i] = bc; bc += hs[i]->host.nchunks;
         single.start[i] = i;
     }
-    tiles.start[n] = bt; zero.start[n] = bz; chunks.start[n] = bc; single.start[n] = n;
-    tiles.n = zero.n = chunks.n = single.n = n;
+    tiles.start[n] = bt; single.start[n] = n;
+    tiles.n = single.n = n;
 }
 
 void enqueue_steps(mpm_handle *const *hs, int n, int steps, hipStream_t s) {
-    WorkTab tiles, zero, chunks, single;
-    make_tables(hs, n, tiles, zero, chunks, single);
+    WorkTab tiles, single;
+    make_tables(hs, n, tiles, single);
     const Layout &L = hs[0]->L;
-    for (int k = 0; k < steps; ++k) launch_step(L.dim, L.shape, L.prec, tiles, zero, chunks, single, s);
+    for (int k = 0; k < steps; ++k) launch_step(L.dim, L.shape, L.prec, tiles, single, s);
 }
 
 int read_dynamic(mpm_handle *h, ProbDev *out, hipStream_t s) {
@@ -304,13 +303,15 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
     P.basetab = (uint32_t *)(H->ws + L.off_basetab);
     P.count = (uint32_t *)(H->ws + L.off_count);
     P.blocksum = (uint32_t *)(H->ws + L.off_blocksum);
-    P.gA = H->ws + L.off_gA;
-    P.gB = H->ws + L.off_gB;
+    for (int p = 0; p < 2; ++p) {
+        P.gA[p] = H->ws + L.off_gA[p];
+        P.gB[p] = H->ws + L.off_gB[p];
+    }
+    P.ttot = (uint32_t *)(H->ws + L.off_ttot);
+    P.tbase = (uint32_t *)(H->ws + L.off_tbase);
     P.nflag = (uint8_t *)(H->ws + L.off_nflag);
     P.nrm = H->ws + L.off_nrm;
     P.partials = (double *)(H->ws + L.off_partials);
-    P.zero_base = H->ws + L.off_gA;
-    P.zero_bytes = (long long)(L.off_zero_end - L.off_gA);
     P.parity = 1;      // the unsorted input goes to parity 1, the sort writes parity 0
     P.active = 1;
 
@@ -401,7 +402,8 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
         st = hip_ok(hipMemcpy(P.nflag, flag.data(), (size_t)L.nnodes, hipMemcpyHostToDevice));
         if (!st) st = hip_ok(hipMemcpy(P.nrm, nrm.data(), nrm.size(), hipMemcpyHostToDevice));
     }
-    if (!st) st = hip_ok(hipMemsetAsync(P.zero_base, 0, (size_t)P.zero_bytes, s));
+    // both grid buffers, the histogram and the tile totals start at zero
+    if (!st) st = hip_ok(hipMemsetAsync(H->ws + L.off_gA[0], 0, L.off_zero_end - L.off_gA[0], s));
     if (!st) st = hip_ok(hipMemcpyAsync(H->dev, &P, sizeof(ProbDev), hipMemcpyHostToDevice, s));
     if (!st) {
         launch_init(dim, d->shape, d->precision, H->dev, P, s);
@@ -427,13 +429,13 @@ int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps, voi
         maxn = std::max<long long>(maxn, n_steps[i]);
     }
     hipStream_t s = (hipStream_t)hip_stream;
-    WorkTab tiles, zero, chunks, single;
-    make_tables(hs, n, tiles, zero, chunks, single);
+    WorkTab tiles, single;
+    make_tables(hs, n, tiles, single);
     std::vector<long long> nn(n);
     for (int i = 0; i < n; ++i) nn[i] = n_steps[i];
     launch_arm(single, nn.data(), s);
     for (long long k = 0; k < maxn; ++k)
-        launch_step(hs[0]->L.dim, hs[0]->L.shape, hs[0]->L.prec, tiles, zero, chunks, single, s);
+        launch_step(hs[0]->L.dim, hs[0]->L.shape, hs[0]->L.prec, tiles, single, s);
     return hip_ok(hipGetLastError());
 }
 
@@ -442,8 +444,8 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
     if (h->reported_err) return MPM_E_STATE;
     hipStream_t s = (hipStream_t)hip_stream;
     mpm_handle *one[1] = {h};
-    WorkTab tiles, zero, chunks, single;
-    make_tables(one, 1, tiles, zero, chunks, single);
+    WorkTab tiles, single;
+    make_tables(one, 1, tiles, single);
     const bool to_end = n_steps <= 0;
     if (to_end && !(h->host.t_end > 0)) return MPM_E_ARG;
     const long long armed = to_end ? (1LL << 60) : n_steps;
@@ -601,13 +603,13 @@ int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stre
     return st;
 }
 
-int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[8], void *hip_stream) {
+int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[6], void *hip_stream) {
     if (!h || n_steps <= 0 || !ms_per_sweep) return MPM_E_ARG;
     if (h->reported_err) return MPM_E_STATE;
     hipStream_t s = (hipStream_t)hip_stream;
     mpm_handle *one[1] = {h};
-    WorkTab tiles, zero, chunks, single;
-    make_tables(one, 1, tiles, zero, chunks, single);
+    WorkTab tiles, single;
+    make_tables(one, 1, tiles, single);
     const long long armed = n_steps;
     launch_arm(single, &armed, s);
     hipEvent_t ev[kSweeps + 1];
@@ -618,7 +620,7 @@ int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[8], voi
     for (long long k = 0; k < n_steps && !st; ++k) {
         st = hip_ok(hipEventRecord(ev[0], s));
         for (int part = 0; part < kSweeps && !st; ++part) {
-            launch_part(h->L.dim, h->L.shape, h->L.prec, part, tiles, zero, chunks, single, s);
+            launch_part(h->L.dim, h->L.shape, h->L.prec, part, tiles, single, s);
             st = hip_ok(hipEventRecord(ev[part + 1], s));
         }
         if (!st) st = hip_ok(hipEventSynchronize(ev[kSweeps]));

@@ -39,8 +39,10 @@ enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_W
 // Diagnostic counters (u64).
 enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2, DG_WIDE = 3 };
 
-// Per-tile partial results of the update sweep (doubles).
-enum { PT_VMAX = 0, PT_CMAX = 1, PT_M = 2, PT_MV = 3 /* 3 */, PT_ME = 6, PT_MK = 7, PT_N = 8 };
+
+// Per-tile partial results of the update sweep (doubles, stored q-major):
+// squared max speed, squared max sound speed, mass, momentum (3), M e, M v^2/2.
+enum { PT_N = 8 };
 
 // Particle fields stored per parity (arrays of `real`).
 enum { PF_X = 0, PF_V = 3, PF_M = 6, PF_RHO = 7, PF_E = 8, PF_G = 9, PF_N = 18 };
@@ -54,7 +56,7 @@ constexpr int kBlock = 256;          // threads per workgroup in every sweep
 constexpr int kScanItems = 16;       // cells per thread in the scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kMaxBatch = 64;        // problems per batched launch
-constexpr int kSweeps = 8;           // kernels per step: zero, p2g, g2p, scan a/b/c, update, finalize
+constexpr int kSweeps = 6;           // kernels per step: p2g, g2p, tile scan, cell scan, update, finalize
 
 struct ProbDev {
     // ---- static geometry and parameters (written once at init)
@@ -84,20 +86,21 @@ struct ProbDev {
     uint32_t *basetab;        // per tile: first rank of its particles in each footprint cell
     uint32_t *count;          // per-cell histogram of the new keys
     uint32_t *offs[2];        // exclusive prefix of counts, per parity (+1 entry)
-    uint32_t *blocksum;       // scan chunk sums
-    void *gA;                 // m, p[d], I[d]: (1 + 2 dim) * nnodes acc words
-    void *gB;                 // p2[d]: dim * nnodes acc words
+    uint32_t *blocksum;       // scan chunk sums (initial sort only)
+    uint32_t *ttot;           // per tile: particles of the next order in the tile
+    uint32_t *tbase;          // exclusive prefix of ttot (ntiles + 1)
+    void *gA[2];              // per step parity: m, p[d], I[d]: (1 + 2 dim) * nnodes acc words
+    void *gB[2];              // per step parity: p2[d]: dim * nnodes acc words
+    double *partials;         // PT_N * ntiles, q-major
     uint8_t *nflag;
     void *nrm;                // dim * nnodes real, or null
-    double *partials;         // ntiles * PT_N
-    void *zero_base;          // [zero_base, zero_base + zero_bytes) cleared each step
-    long long zero_bytes;
 
     // ---- per-step state (device-updated)
     double t, dt, dt_last;
     long long step, steps_left;
     int active, parity;
     uint32_t err, pad1;
+
     unsigned long long diag[4];
     double cons[6];
 };

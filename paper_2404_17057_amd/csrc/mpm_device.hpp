@@ -253,7 +253,7 @@ __device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
                                         typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     using A = typename PrecT<PREC>::acc;
-    const A *g = (const A *)P->gA;
+    const A *g = (const A *)P->gA[P->parity];
     const long long NN = P->nnodes;
     const R m = from_acc<PREC>(g[node], P->q_m, flags);
     R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
@@ -280,8 +280,8 @@ __device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
                                         typename PrecT<PREC>::real v2[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     using A = typename PrecT<PREC>::acc;
-    const A *gA = (const A *)P->gA;
-    const A *gB = (const A *)P->gB;
+    const A *gA = (const A *)P->gA[P->parity];
+    const A *gB = (const A *)P->gB[P->parity];
     const long long NN = P->nnodes;
     const R m = from_acc<PREC>(gA[node], P->q_m, flags);
     R p[3] = {0, 0, 0};

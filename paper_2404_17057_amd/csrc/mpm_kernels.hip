@@ -5,16 +5,23 @@
 // space).  Particles are kept sorted by the tile-major key of their cell, so
 // the particles of a tile are one contiguous range.
 //
-// Per step (all problems of a batch together):
-//   k_zero      clear the grid accumulators and the cell histogram
-//   k_p2g       S1: P2G mass, momentum, impulse dt*f        (Sec. 3 (ii))
+// Per step (all problems of a batch together), six launches:
+//   k_p2g       S1: P2G mass, momentum, impulse dt*f (Sec. 3 (ii)); also
+//               clears the cell histogram of its tile and the frame nodes of
+//               the other grid buffer for the next step
 //   k_g2p       S2: conditions + update on the tile load, G2P, FLIP velocity
-//               update, new cell key and rank, P2G of M V'   (Sec. 3 (iii)-(vi))
-//   k_scan_*    exclusive prefix of the new cell histogram
+//               update, new cell key and rank, P2G of M V' (Sec. 3 (iii)-(vi));
+//               per-tile totals of the new order
+//   k_tilescan  one workgroup per problem: tile bases of the new order
+//   k_cellscan  per tile: offsets of the new order (tile base + cell prefix)
 //   k_update    S3: conditions on p2 on the tile load, G2PD, energy /
 //               density update, move, recycling, scatter into the new sorted
-//               order, per-tile CFL maxima and FP64 sums (Sec. 3 (vii)-(xi))
-//   k_finalize  dt of the next step, t, conserved sums, parity flip (xii)
+//               order; CFL maxima (atomic max of the float bits, exact and
+//               order-free) and FP64 sums per problem (Sec. 3 (vii)-(xi))
+//   k_finalize  one lane per problem: next dt, t, parity (xii)
+// Grid accumulators and particle arrays are double-buffered by step parity.
+// (An in-kernel "last workgroup" hand-off would need an agent-scope release
+// per workgroup, which on this GPU writes back the whole L2 of an XCD.)
 //
 // P2G (S1, S2): one lane per cell.  The lane walks the particles of its
 // cell and sums their contributions to the cell's stencil nodes in
@@ -30,26 +37,7 @@ namespace mpm {
 
 template <typename R> struct R3 { R v[3]; };
 
-// ------------------------------------------------------------------- zero --
-__global__ __launch_bounds__(kBlock) void k_zero(WorkTab wt) {
-    const int pi = find_prob(wt, blockIdx.x);
-    ProbDev *P = wt.prob[pi];
-    if (!P->active) return;
-    const int b = blockIdx.x - wt.start[pi];
-    const int nb = wt.start[pi + 1] - wt.start[pi];
-    uint4 *base = (uint4 *)P->zero_base;
-    const long long n16 = P->zero_bytes / 16;
-    const uint4 z = make_uint4(0, 0, 0, 0);
-    for (long long i = (long long)b * kBlock + threadIdx.x; i < n16; i += (long long)nb * kBlock)
-        base[i] = z;
-}
-
-// Number of zero-kernel workgroups for a problem.
-int zero_blocks(const ProbDev &h) {
-    long long n16 = h.zero_bytes / 16;
-    long long nb = (n16 + kBlock * 8 - 1) / (kBlock * 8);
-    return (int)(nb < 1 ? 1 : (nb > 4096 ? 4096 : nb));
-}
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total);
 
 // Tile coordinates of tile t and this lane's cell.
 template <int DIM>
@@ -158,6 +146,30 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     uint32_t flags = 0;
     unsigned long long mismatch = 0;
 
+    // Next order: clear this tile's cell histogram and tile total (read by
+    // nothing in this sweep, filled by S2).  Next step's grid: clear the
+    // frame nodes of this tile's footprint in the other buffer (the owned
+    // nodes are overwritten by stores).
+    P->count[key] = 0;
+    if (threadIdx.x == 0) P->ttot[t] = 0;
+    {
+        A *gAn = (A *)P->gA[par ^ 1];
+        A *gBn = (A *)P->gB[par ^ 1];
+        const long long NN = P->nnodes;
+        for (int li = threadIdx.x; li < G::TN; li += kBlock) {
+            const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
+            const bool own = ix >= G::W - 1 && ix < G::TX && iy >= G::W - 1 && iy < G::TY &&
+                             (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
+            const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
+            if (own || gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
+            const long long node = node_index(P, gx, gy, gz);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gAn[q * NN + node] = (A)0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) gBn[a * NN + node] = (A)0;
+        }
+    }
+
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
         L acc[G::WP][NQ];
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
         // contributions go straight to the global grid.
-        A *g = (A *)P->gA;
+        A *g = (A *)P->gA[par];
         const long long NN = P->nnodes;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
@@ -247,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, NQ>(P, c0, tile, (A *)P->gA, flags);
+    flush_tile<DIM, SHAPE, PREC, NQ>(P, c0, tile, (A *)P->gA[par], flags);
     if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
 }
@@ -400,7 +412,12 @@ __device__ __forceinline__ void s2_key_rank(const ProbDev *P, uint32_t k, const 
     const uint32_t nk = cell_key<DIM>(P, cn);
     P->key[k] = nk;
     const int dl = dest_local<DIM>(c0, cn);
-    P->rank[k] = dl >= 0 ? atomicAdd(&hist[dl], 1u) : (atomicAdd(&P->count[nk], 1u) | kRankGlobal);
+    if (dl >= 0) {
+        P->rank[k] = atomicAdd(&hist[dl], 1u);
+    } else {
+        P->rank[k] = atomicAdd(&P->count[nk], 1u) | kRankGlobal;
+        atomicAdd(&P->ttot[nk / Tile<DIM>::CELLS], 1u);
+    }
 }
 
 template <int DIM, int SHAPE, int PREC>
@@ -524,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     if (mismatch) {
         // Particles whose cell changed between sort and use: G2P from the
         // global grid, P2G straight to the global grid.
-        A *g = (A *)P->gB;
+        A *g = (A *)P->gB[par];
         const long long NN = P->nnodes;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
@@ -557,25 +574,83 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                     }
         }
     }
+    __shared__ uint32_t ttl[27];
+    if (threadIdx.x < 27) ttl[threadIdx.x] = 0;
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, DIM>(P, c0, tile, (A *)P->gB, flags);
+    flush_tile<DIM, SHAPE, PREC, DIM>(P, c0, tile, (A *)P->gB[par], flags);
     // One global histogram atomic per destination cell of this tile: the
     // tile's particles of that cell get the ranks base .. base + hist - 1.
+    // Tile totals are gathered per destination tile (the tile and its
+    // neighbours) before going global.
     uint32_t *bt = P->basetab + (long long)t * ND;
+    const int ttx = c0[0] / G::TX, tty = c0[1] / G::TY, ttz = c0[2] / G::TZ;
     for (int i = threadIdx.x; i < ND; i += kBlock) {
         const uint32_t cnt = hist[i];
         if (!cnt) continue;
         const int lx = i % (G::TX + 2), ly = (i / (G::TX + 2)) % (G::TY + 2), lz = i / ((G::TX + 2) * (G::TY + 2));
         const int cn[3] = {c0[0] + lx - 1, c0[1] + ly - 1, DIM == 3 ? c0[2] + lz - 1 : 0};
         bt[i] = atomicAdd(&P->count[cell_key<DIM>(P, cn)], cnt);
+        const int dx = (cn[0] >= c0[0] + G::TX) - (cn[0] < c0[0]);
+        const int dy = (cn[1] >= c0[1] + G::TY) - (cn[1] < c0[1]);
+        const int dz = DIM == 3 ? (cn[2] >= c0[2] + G::TZ) - (cn[2] < c0[2]) : 0;
+        atomicAdd(&ttl[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)], cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x < 27 && ttl[threadIdx.x]) {
+        const int i = threadIdx.x;
+        const int dx = i % 3 - 1, dy = (i / 3) % 3 - 1, dz = i / 9 - 1;
+        const long long tile = ((long long)(ttz + dz) * P->ntile[1] + (tty + dy)) * P->ntile[0] + (ttx + dx);
+        atomicAdd(&P->ttot[tile], ttl[i]);
     }
     if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
+
+}
+
+// Wave-level reductions over the 64 lanes of a wavefront.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Block reduction of the PT_N partials (entries 0-1 max, the rest sums);
+// the result is valid in thread 0.  red: PT_N * (blockDim / 64) doubles.
+__device__ __forceinline__ void block_reduce_partials(double part[PT_N], double *red) {
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < PT_N; ++q) part[q] = q < 2 ? wave_max(part[q]) : wave_sum(part[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < PT_N; ++q) red[q * nw + w] = part[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < PT_N; ++q) {
+            double r = red[q * nw];
+            for (int i = 1; i < nw; ++i) r = q < 2 ? fmax(r, red[q * nw + i]) : r + red[q * nw + i];
+            part[q] = r;
+        }
+    }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------ scan --
 // Exclusive prefix of the cell histogram into offs[parity ^ 1].
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
     // Hillis-Steele over the 256 thread totals in LDS.
     sh[threadIdx.x] = v;
     __syncthreads();
@@ -652,7 +727,50 @@ __global__ __launch_bounds__(kBlock) void k_scan_c(WorkTab wt) {
     if (ch == P->nchunks - 1 && threadIdx.x == 0) out[P->ncells_pad] = (uint32_t)P->np;
 }
 
-// -------------------------------------------------------------------- S3 --
+// One workgroup per problem: exclusive prefix of the per-tile totals of the
+// next order (each thread scans a run of consecutive tiles; wave scans of
+// the run totals, then one scan of the wave totals).
+__global__ __launch_bounds__(1024) void k_tilescan(WorkTab wt) {
+    __shared__ uint32_t wtot[16];
+    ProbDev *P = wt.prob[blockIdx.x];
+    if (!P->active) return;
+    const int n = P->ntiles;
+    const int per = (n + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    uint32_t run = 0;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < n) run += P->ttot[b0 + i];
+    const uint32_t incl = wave_incl_scan(run);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += wtot[i];
+    uint32_t ex = wbase + incl - run;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < n) {
+            P->tbase[b0 + i] = ex;
+            ex += P->ttot[b0 + i];
+        }
+    if (threadIdx.x == 1023) P->tbase[n] = wbase + incl;
+}
+
+// Per tile: offsets of the next order, tile base + prefix of the tile's
+// cell counts (written into offs[parity ^ 1]).
+__global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
+    __shared__ uint32_t sh[kBlock];
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int t = blockIdx.x - wt.start[pi];
+    uint32_t *out = P->offs[P->parity ^ 1];
+    const uint32_t c = (uint32_t)t * kBlock + threadIdx.x;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(P->count[c], sh, total);
+    out[c] = P->tbase[t] + ex;
+    if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = P->tbase[P->ntiles];
+}
+
 template <typename T>
 __device__ __forceinline__ T block_reduce_sum(T v, T *sh) {
     sh[threadIdx.x] = v;
@@ -678,6 +796,57 @@ __device__ __forceinline__ T block_reduce_max(T v, T *sh) {
     return r;
 }
 
+// -------------------------------------------------------------- finalize --
+// Next time step from the per-tile maxima of the step just done (Sec. 2.2,
+// CFL; Sec. 3 (xi)-(xii)), time and conserved sums.  Thread 0 of one
+// workgroup per problem holds the reduced partials.
+__device__ void finalize_problem(ProbDev *P, bool advance, const double part[PT_N]) {
+    const double vmax = sqrt(part[0]);
+    const double cmax = sqrt(part[1]);
+    if (advance) {
+        P->dt_last = P->dt;
+        P->t = P->t + P->dt;
+        P->step += 1;
+        P->steps_left -= 1;
+        P->parity ^= 1;
+    }
+    double dtn = (vmax + cmax > 0.0) ? P->cfl * P->h / (vmax + cmax) : 0.0;
+    if (P->t_end > 0.0) {
+        const double rest = P->t_end - P->t;
+        if (rest < dtn) dtn = rest;
+        if (dtn < 0.0) dtn = 0.0;
+    }
+    P->dt = dtn;
+    for (int c = 0; c < 6; ++c) P->cons[c] = part[2 + c];
+    P->active = (P->steps_left > 0 && P->err == 0 && dtn > 0.0 &&
+                 (P->t_end <= 0.0 || P->t < P->t_end)) ? 1 : 0;
+}
+
+// Reduction of the per-tile partials of one problem by one workgroup.
+__device__ __forceinline__ void reduce_tile_partials(const ProbDev *P, double part[PT_N], double *red) {
+#pragma unroll
+    for (int q = 0; q < PT_N; ++q) part[q] = 0.0;
+    for (int t = threadIdx.x; t < P->ntiles; t += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < PT_N; ++q) {
+            const double v = P->partials[(long long)q * P->ntiles + t];
+            part[q] = q < 2 ? fmax(part[q], v) : part[q] + v;
+        }
+    block_reduce_partials(part, red);
+}
+
+constexpr int kWideBlock = 1024;
+
+__global__ __launch_bounds__(kWideBlock) void k_finalize(WorkTab wt) {
+    __shared__ double red[PT_N * (kWideBlock / 64)];
+    ProbDev *P = wt.prob[blockIdx.x];
+    if (!P->active) return;
+    double part[PT_N];
+    reduce_tile_partials(P, part, red);
+    if (threadIdx.x == 0) finalize_problem(P, true, part);
+}
+
+// -------------------------------------------------------------------- S3 --
 // Running per-tile results of S3.
 struct S3Sums {
     double vmax2, cmax2, M, MV[3], ME, MK;
@@ -830,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     constexpr int ND = DestFoot<DIM>::N;
     __shared__ R stage[NF * G::TN];
     __shared__ uint32_t sbase[ND];
-    __shared__ double red[kBlock];
+    __shared__ double red[PT_N * (kBlock / 64)];
 
     const int pi = find_prob(wt, blockIdx.x);
     ProbDev *P = wt.prob[pi];
@@ -877,72 +1046,18 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
         }
     }
 
-    double *pt = P->partials + (long long)t * PT_N;
-    // squared maxima: one square root per tile instead of per particle
-    const double r0 = sqrt(block_reduce_max(sums.vmax2, red));
-    const double c2 = block_reduce_max(sums.cmax2, red);
-    const double r1 = c2 > 0.0 ? sqrt(c2) : 0.0;
-    const double r2 = block_reduce_sum(sums.M, red);
-    double rv[3];
-    for (int a = 0; a < 3; ++a) rv[a] = block_reduce_sum(sums.MV[a], red);
-    const double r6 = block_reduce_sum(sums.ME, red);
-    const double r7 = block_reduce_sum(sums.MK, red);
-    if (threadIdx.x == 0) {
-        pt[PT_VMAX] = r0; pt[PT_CMAX] = r1; pt[PT_M] = r2;
-        pt[PT_MV] = rv[0]; pt[PT_MV + 1] = rv[1]; pt[PT_MV + 2] = rv[2];
-        pt[PT_ME] = r6; pt[PT_MK] = r7;
-    }
+    // Per-tile partials (one plain store each): squared CFL maxima and the
+    // FP64 sums; the finalize kernel reduces them.
+    double part[PT_N] = {sums.vmax2, sums.cmax2, sums.M, sums.MV[0], sums.MV[1], sums.MV[2], sums.ME, sums.MK};
+    block_reduce_partials(part, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < PT_N; ++q) P->partials[(long long)q * P->ntiles + t] = part[q];
     const uint32_t errs = flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW | ERR_INTERNAL);
     if (errs) atomicOr((uint32_t *)&P->err, errs);
     if (sums.mis) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], sums.mis);
     if (sums.rec) atomicAdd((unsigned long long *)&P->diag[DG_RECYCLE], sums.rec);
     if (sums.wall) atomicAdd((unsigned long long *)&P->diag[DG_WALL], sums.wall);
-}
-
-// -------------------------------------------------------------- finalize --
-// One workgroup per problem: per-tile partials -> CFL time step of the next
-// step (Sec. 2.2, CFL; Sec. 3 (xi)-(xii)), time, conserved sums, parity.
-__device__ void finalize_problem(ProbDev *P, bool advance) {
-    __shared__ double red[kBlock];
-    double vmax = 0, cmax = 0, s[6] = {0, 0, 0, 0, 0, 0};
-    for (int tt = threadIdx.x; tt < P->ntiles; tt += kBlock) {
-        const double *pt = P->partials + (long long)tt * PT_N;
-        vmax = fmax(vmax, pt[PT_VMAX]);
-        cmax = fmax(cmax, pt[PT_CMAX]);
-        s[0] += pt[PT_M];
-        s[1] += pt[PT_MV]; s[2] += pt[PT_MV + 1]; s[3] += pt[PT_MV + 2];
-        s[4] += pt[PT_ME]; s[5] += pt[PT_MK];
-    }
-    vmax = block_reduce_max(vmax, red);
-    cmax = block_reduce_max(cmax, red);
-    double tot[6];
-    for (int c = 0; c < 6; ++c) tot[c] = block_reduce_sum(s[c], red);
-    if (threadIdx.x == 0) {
-        if (advance) {
-            P->dt_last = P->dt;
-            P->t = P->t + P->dt;
-            P->step += 1;
-            P->steps_left -= 1;
-            P->parity ^= 1;
-        }
-        double dtn = (vmax + cmax > 0.0) ? P->cfl * P->h / (vmax + cmax) : 0.0;
-        if (P->t_end > 0.0) {
-            const double rest = P->t_end - P->t;
-            if (rest < dtn) dtn = rest;
-            if (dtn < 0.0) dtn = 0.0;
-        }
-        P->dt = dtn;
-        for (int c = 0; c < 6; ++c) P->cons[c] = tot[c];
-        P->active = (P->steps_left > 0 && P->err == 0 && dtn > 0.0 &&
-                     (P->t_end <= 0.0 || P->t < P->t_end)) ? 1 : 0;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_finalize(WorkTab wt) {
-    const int pi = find_prob(wt, blockIdx.x);
-    ProbDev *P = wt.prob[pi];
-    if (!P->active) return;
-    finalize_problem(P, true);
 }
 
 // Arm problems for a run of steps: steps_left and the active flag.
@@ -985,11 +1100,11 @@ __global__ __launch_bounds__(kBlock) void k_init_permute(ProbDev *P) {
     P->pid[0][slot] = P->pid[1][k];
 }
 
-// Initial per-tile maxima and sums (parity 0, sorted): reuses the partials.
+// Initial maxima and sums of the sorted state (parity 0).
 template <int DIM, int SHAPE, typename R>
 __global__ __launch_bounds__(kBlock) void k_init_stats(ProbDev *P) {
     using G = Geo<DIM, SHAPE>;
-    __shared__ double red[kBlock];
+    __shared__ double red[PT_N * (kBlock / 64)];
     const int t = blockIdx.x;
     const uint32_t pbeg = P->offs[0][(uint32_t)t * G::CELLS], pend = P->offs[0][(uint32_t)(t + 1) * G::CELLS];
     double vmax = 0, cmax = 0, s[6] = {0, 0, 0, 0, 0, 0};
@@ -1010,21 +1125,20 @@ __global__ __launch_bounds__(kBlock) void k_init_stats(ProbDev *P) {
         s[4] += (double)M * (double)e;
         s[5] += 0.5 * (double)M * v2;
     }
-    double *pt = P->partials + (long long)t * PT_N;
-    const double r0 = block_reduce_max(vmax, red);
-    const double r1 = block_reduce_max(cmax, red);
-    double tot[6];
-    for (int c = 0; c < 6; ++c) tot[c] = block_reduce_sum(s[c], red);
-    if (threadIdx.x == 0) {
-        pt[PT_VMAX] = r0; pt[PT_CMAX] = r1; pt[PT_M] = tot[0];
-        pt[PT_MV] = tot[1]; pt[PT_MV + 1] = tot[2]; pt[PT_MV + 2] = tot[3];
-        pt[PT_ME] = tot[4]; pt[PT_MK] = tot[5];
-    }
+    double part[PT_N] = {vmax * vmax, cmax * cmax, s[0], s[1], s[2], s[3], s[4], s[5]};
+    block_reduce_partials(part, red);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < PT_N; ++q) P->partials[(long long)q * P->ntiles + t] = part[q];
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_finalize(ProbDev *P) {
-    finalize_problem(P, false);
-    if (threadIdx.x == 0) { P->active = 0; P->parity = 0; }
+__global__ __launch_bounds__(kWideBlock) void k_init_finalize(ProbDev *P) {
+    __shared__ double red[PT_N * (kWideBlock / 64)];
+    double part[PT_N];
+    reduce_tile_partials(P, part, red);
+    if (threadIdx.x != 0) return;
+    finalize_problem(P, false, part);
+    P->active = 0;
+    P->parity = 0;
 }
 
 // ------------------------------------------------------------ diagnostics --
@@ -1036,8 +1150,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, dou
     const long long node = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long NN = P->nnodes;
     if (node >= NN) return;
-    const A *gA = (const A *)P->gA;
-    const A *gB = (const A *)P->gB;
+    const A *gA = (const A *)P->gA[P->parity ^ 1];
+    const A *gB = (const A *)P->gB[P->parity ^ 1];
     const double qm = PrecT<PREC>::fixed ? P->q_m : 1.0, qp = PrecT<PREC>::fixed ? P->q_p : 1.0;
     const double dtl = P->dt_last > 0 ? P->dt_last : 1.0;
     const uint8_t fl = P->nflag[node];
@@ -1071,26 +1185,23 @@ __global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, dou
 // ------------------------------------------------------------- launchers --
 static inline dim3 grid1(int n) { return dim3((unsigned)n); }
 
-// One sweep of the step (part 0..7 in launch order).
+// One sweep of the step (part 0..5 in launch order).
 template <int DIM, int SHAPE, int PREC>
-void launch_part_t(int part, const WorkTab &tiles, const WorkTab &zero, const WorkTab &chunks,
-                   const WorkTab &single, hipStream_t s) {
+void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
+    const dim3 grid(tiles.start[tiles.n]);
     switch (part) {
-    case 0: hipLaunchKernelGGL(k_zero, grid1(zero.start[zero.n]), dim3(kBlock), 0, s, zero); break;
-    case 1: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
-    case 2: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
-    case 3: hipLaunchKernelGGL(k_scan_a, grid1(chunks.start[chunks.n]), dim3(kBlock), 0, s, chunks); break;
-    case 4: hipLaunchKernelGGL(k_scan_b, grid1(single.start[single.n]), dim3(kBlock), 0, s, single); break;
-    case 5: hipLaunchKernelGGL(k_scan_c, grid1(chunks.start[chunks.n]), dim3(kBlock), 0, s, chunks); break;
-    case 6: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid1(tiles.start[tiles.n]), dim3(kBlock), 0, s, tiles); break;
-    default: hipLaunchKernelGGL(k_finalize, grid1(single.start[single.n]), dim3(kBlock), 0, s, single); break;
+    case 0: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 1: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 2: hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single); break;
+    case 3: hipLaunchKernelGGL(k_cellscan, grid, dim3(kBlock), 0, s, tiles); break;
+    case 4: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    default: hipLaunchKernelGGL(k_finalize, dim3(single.n), dim3(kWideBlock), 0, s, single); break;
     }
 }
 
 template <int DIM, int SHAPE, int PREC>
-void launch_step_t(const WorkTab &tiles, const WorkTab &zero, const WorkTab &chunks,
-                   const WorkTab &single, hipStream_t s) {
-    for (int part = 0; part < kSweeps; ++part) launch_part_t<DIM, SHAPE, PREC>(part, tiles, zero, chunks, single, s);
+void launch_step_t(const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
+    for (int part = 0; part < kSweeps; ++part) launch_part_t<DIM, SHAPE, PREC>(part, tiles, single, s);
 }
 
 template <int DIM, int SHAPE, int PREC>
@@ -1108,7 +1219,7 @@ void launch_init_t(ProbDev *dP, const ProbDev &h, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_c, dim3(h.nchunks), dim3(kBlock), 0, s, ch);
     if (nb) hipLaunchKernelGGL((k_init_permute<DIM, R>), dim3(nb), dim3(kBlock), 0, s, dP);
     hipLaunchKernelGGL((k_init_stats<DIM, SHAPE, R>), dim3(h.ntiles), dim3(kBlock), 0, s, dP);
-    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(kBlock), 0, s, dP);
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(kWideBlock), 0, s, dP);
 }
 
 template <int DIM, int PREC>
@@ -1147,16 +1258,15 @@ void launch_grid_diag_t(ProbDev *dP, const ProbDev &h, int which, double *out, h
         }                                                                         \
     } while (0)
 
-void launch_step(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &zero,
-                 const WorkTab &chunks, const WorkTab &single, hipStream_t s) {
-#define CALL_STEP(D, S, Pr) launch_step_t<D, S, Pr>(tiles, zero, chunks, single, s)
+void launch_step(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
+#define CALL_STEP(D, S, Pr) launch_step_t<D, S, Pr>(tiles, single, s)
     MPM_DISPATCH(dim, shape, prec, CALL_STEP);
 #undef CALL_STEP
 }
 
-void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &zero,
-                 const WorkTab &chunks, const WorkTab &single, hipStream_t s) {
-#define CALL_PART(D, S, Pr) launch_part_t<D, S, Pr>(part, tiles, zero, chunks, single, s)
+void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &single,
+                 hipStream_t s) {
+#define CALL_PART(D, S, Pr) launch_part_t<D, S, Pr>(part, tiles, single, s)
     MPM_DISPATCH(dim, shape, prec, CALL_PART);
 #undef CALL_PART
 }

@@ -28,7 +28,7 @@ G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS = range(7)
 EXPORTS = ["mpm_footprint", "mpm_init", "mpm_step", "mpm_step_batch", "mpm_read_fields",
            "mpm_read_grid", "mpm_status", "mpm_counters", "mpm_profile_step", "mpm_grid_shape",
            "mpm_destroy", "mpm_strerror"]
-SWEEPS = ["clear", "p2g", "g2p_p2g", "scan_a", "scan_b", "scan_c", "update", "finalize"]
+SWEEPS = ["p2g", "g2p_p2g", "tilescan", "cellscan", "update", "finalize"]
 
 
 class Desc(C.Structure):
@@ -254,7 +254,7 @@ class Simulation:
 
     def profile(self, n: int) -> Dict[str, float]:
         """Average milliseconds per sweep over n real steps (HIP events)."""
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * len(SWEEPS))()
         rc = lib().mpm_profile_step(self._h, int(n), ms, self._sp())
         if rc:
             raise MPMError(rc, "mpm_profile_step")

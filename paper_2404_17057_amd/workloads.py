@@ -325,3 +325,95 @@ WORKLOADS = {
     "blast3d": blast3d,
     "quadrant": quadrant,
 }
+
+
+# ------------------------------------------------------------------ serving --
+
+@dataclasses.dataclass
+class RequestSpec:
+    """One request of the serving stream: arrival time (s), family, sizes,
+    physical parameters and step count.  The particle cloud is built on
+    admission by `build_request`."""
+
+    req_id: int
+    arrival: float
+    family: str            # "sod" | "quadrant" | "cylinder"
+    nx: int
+    ny: int
+    steps: int
+    seed: int
+    mach: float = 3.0
+
+
+def request_stream(n=1000, rate=200.0, seed=2404) -> list:
+    """Poisson stream of `n` requests at `rate` per second.  Families are drawn
+    uniformly: Sod tubes nx in {256, ..., 4096} with ny = max(8, nx/256);
+    2x2-quadrant Riemann problems on n^2 grids, n in {128, ..., 1024}; Mach
+    2-4 cylinders nx in {256, 512, 1024} by nx/2.  Steps uniform in 200..2000."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        fam = ("sod", "quadrant", "cylinder")[int(rng.integers(3))]
+        if fam == "sod":
+            nx = int(rng.choice([256, 512, 1024, 2048, 4096]))
+            ny = max(8, nx // 256)
+        elif fam == "quadrant":
+            nx = int(rng.choice([128, 256, 512, 1024]))
+            ny = nx
+        else:
+            nx = int(rng.choice([256, 512, 1024]))
+            ny = nx // 2
+        out.append(RequestSpec(req_id=i, arrival=t, family=fam, nx=nx, ny=ny,
+                               steps=int(rng.integers(200, 2001)),
+                               seed=int(rng.integers(1 << 31)),
+                               mach=float(rng.uniform(2.0, 4.0))))
+    return out
+
+
+class LatticeCache:
+    """Jittered particle lattices (and cylinder masks / normals) per grid,
+    built once with the default seed and shared by all requests of that grid;
+    the per-request draws set the initial states, Mach number and steps."""
+
+    def __init__(self):
+        self._c = {}
+
+    def get(self, key, make):
+        if key not in self._c:
+            self._c[key] = make()
+        return self._c[key]
+
+
+def build_request(spec: RequestSpec, cache: Optional[LatticeCache] = None) -> Problem:
+    cache = cache or LatticeCache()
+    gamma = 1.4
+    if spec.family == "sod":
+        def make():
+            return sod(nx=spec.nx, ny=spec.ny, t_end=0.0)
+        base = cache.get(("sod", spec.nx, spec.ny), make)
+        pb = dataclasses.replace(base, steps=spec.steps, seed=spec.seed, name=f"req{spec.req_id}_{base.name}")
+        return pb
+    if spec.family == "quadrant":
+        def make():
+            return quadrant(n=spec.nx)
+        base = cache.get(("quadrant", spec.nx), make)
+        rng = np.random.default_rng(spec.seed)
+        q_rho = rng.uniform(0.1, 2.0, 4)
+        q_p = rng.uniform(0.1, 2.0, 4)
+        q_u = rng.uniform(-0.7, 0.7, (4, 2))
+        x = base.x
+        q = (x[0] >= 0.5).astype(int) + 2 * (x[1] >= 0.5).astype(int)
+        rho = q_rho[q]
+        h = base.h
+        return dataclasses.replace(
+            base, name=f"req{spec.req_id}_{base.name}", v=q_u[q].T.copy(), rho=rho,
+            mass=rho * h * h / 4, eint=q_p[q] / ((gamma - 1.0) * rho), steps=spec.steps, seed=spec.seed)
+    def make():
+        return cylinder(nx=spec.nx, ny=spec.ny, mach=3.0, steps=0)
+    base = cache.get(("cylinder", spec.nx), make)
+    v = np.zeros_like(base.v)
+    v[0] = spec.mach
+    return dataclasses.replace(base, name=f"req{spec.req_id}_{base.name}", v=v,
+                               inflow_u=(spec.mach, 0.0, 0.0), steps=spec.steps, seed=spec.seed)

@@ -1,0 +1,44 @@
+"""Served results equal the same problems run alone (fixed-point precision,
+bit for bit), with requests arriving while others run."""
+import hashlib
+
+import numpy as np
+import pytest
+
+from paper_2404_17057_amd import mpm as G
+from paper_2404_17057_amd import serving as S
+from paper_2404_17057_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_alone_runs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rng = np.random.default_rng(11)
+    specs = []
+    t = 0.0
+    fams = ["sod", "quadrant", "cylinder"]
+    for i in range(10):
+        t += rng.exponential(0.004)
+        fam = fams[i % 3]
+        nx = {"sod": 256, "quadrant": 64, "cylinder": 128}[fam]
+        ny = {"sod": 8, "quadrant": 64, "cylinder": 64}[fam]
+        specs.append(W.RequestSpec(req_id=i, arrival=t, family=fam, nx=nx, ny=ny,
+                                   steps=int(rng.integers(20, 90)), seed=int(rng.integers(1 << 30)),
+                                   mach=float(rng.uniform(2, 4))))
+    cache = W.LatticeCache()
+    build = lambda s: W.build_request(s, cache)
+    be = S.GPUBackend(G.FP32_FIX64)
+    srv = S.Server(be, build, hbm_budget=1 << 30, max_slots=4, steps_per_launch=16)
+    done = srv.run(specs)
+    assert len(done) == len(specs) and all(d.status == 0 for d in done)
+    for d in done:
+        spec = specs[d.req_id]
+        sim = G.Simulation(build(spec), G.FP32_FIX64)
+        sim.step(spec.steps)
+        rho = sim.field(G.F_RHO)
+        assert hashlib.sha256(rho.tobytes()).hexdigest() == d.digest, spec
+    summ = S.summarize(done)
+    assert summ["requests"] == 10
