@@ -5,6 +5,13 @@
 
 namespace mpm {
 
+// Pointers read from the problem descriptor are generic; re-typing them to
+// the global address space lets the compiler use global (not flat) memory
+// instructions, which do not share the LDS wait counter.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GLOBAL_AS T *gmem(T *p) { return (GLOBAL_AS T *)p; }
+template <typename T> __device__ __forceinline__ const GLOBAL_AS T *gmem(const T *p) { return (const GLOBAL_AS T *)p; }
+
 template <int DIM, int SHAPE> struct Geo {
     static constexpr int W = SHAPE == S_B2 ? 3 : 2;          // nodes per axis in a stencil
     static constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
@@ -38,22 +45,67 @@ __device__ __forceinline__ int basis1(R s, int n, R w[3], R dw[3]) {
         w[0] = v;  dw[0] = (R)-1;
         w[1] = u;  dw[1] = (R)1;
     } else {
+        // interior pieces, then the first / last cell by selection (no branches)
+        const bool first = c == 0, last = c == n - 1;
         const R hv2 = (R)0.5 * v * v, hu2 = (R)0.5 * u * u;
-        if (c == 0) {
-            w[0] = v * v;                  dw[0] = (R)-2 * v;
-            w[1] = u * ((R)2 - (R)1.5 * u); dw[1] = (R)2 - (R)3 * u;
-            w[2] = hu2;                     dw[2] = u;
-        } else if (c == n - 1) {
-            w[0] = hv2;                     dw[0] = -v;
-            w[1] = v * ((R)2 - (R)1.5 * v); dw[1] = (R)1 - (R)3 * u;
-            w[2] = u * u;                   dw[2] = (R)2 * u;
-        } else {
-            w[0] = hv2;                     dw[0] = -v;
-            w[1] = (R)0.5 + u * v;          dw[1] = (R)1 - (R)2 * u;
-            w[2] = hu2;                     dw[2] = u;
-        }
+        w[0] = first ? v * v : hv2;
+        dw[0] = first ? (R)-2 * v : -v;
+        w[1] = first ? u * ((R)2 - (R)1.5 * u) : (last ? v * ((R)2 - (R)1.5 * v) : (R)0.5 + u * v);
+        dw[1] = first ? (R)2 - (R)3 * u : (last ? (R)1 - (R)3 * u : (R)1 - (R)2 * u);
+        w[2] = last ? u * u : hu2;
+        dw[2] = last ? (R)2 * u : u;
     }
     return c;
+}
+
+// Loop-invariant parameters of a problem, read from the descriptor at kernel
+// entry, before the kernel's first store, so that the reads are uniform
+// (scalar) loads and the values stay in registers through loops that store
+// to global memory.  Field names match the descriptor's: the helpers below
+// take either.
+struct View {
+    int n[3], nn[3], ntile[3];
+    int face[3][2];
+    int av_form;
+    long long nnodes, np, step;
+    unsigned long long seed;
+    double lo[3], hi[3], h, inv_h, dt, gamma, c0, c1;
+    double q_m, q_p, inv_q_m, inv_q_p;
+    double inflow_rho, inflow_e, inflow_u[3], recycle_mass;
+};
+
+__device__ __forceinline__ View make_view(const ProbDev *P) {
+    View v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v.n[a] = P->n[a];
+        v.nn[a] = P->nn[a];
+        v.ntile[a] = P->ntile[a];
+        v.face[a][0] = P->face[a][0];
+        v.face[a][1] = P->face[a][1];
+        v.lo[a] = P->lo[a];
+        v.hi[a] = P->hi[a];
+        v.inflow_u[a] = P->inflow_u[a];
+    }
+    v.av_form = P->av_form;
+    v.nnodes = P->nnodes;
+    v.np = P->np;
+    v.step = P->step;
+    v.seed = P->seed;
+    v.h = P->h;
+    v.inv_h = P->inv_h;
+    v.dt = P->dt;
+    v.gamma = P->gamma;
+    v.c0 = P->c0;
+    v.c1 = P->c1;
+    v.q_m = P->q_m;
+    v.q_p = P->q_p;
+    v.inv_q_m = P->inv_q_m;
+    v.inv_q_p = P->inv_q_p;
+    v.inflow_rho = P->inflow_rho;
+    v.inflow_e = P->inflow_e;
+    v.recycle_mass = P->recycle_mass;
+    return v;
 }
 
 // Particle stencil: per-axis cells, weights and derivatives.
@@ -62,8 +114,8 @@ template <int DIM, int SHAPE, typename R> struct Stencil {
     R w[3][3], dw[3][3];
 };
 
-template <int DIM, int SHAPE, typename R>
-__device__ __forceinline__ void make_stencil(const ProbDev *P, const R x[3], Stencil<DIM, SHAPE, R> &st) {
+template <int DIM, int SHAPE, typename R, class PP>
+__device__ __forceinline__ void make_stencil(const PP *P, const R x[3], Stencil<DIM, SHAPE, R> &st) {
     const R inv_h = (R)P->inv_h;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -154,7 +206,7 @@ __device__ __forceinline__ void glb_add(float *p, float v) { unsafeAtomicAdd(p, 
 template <int DIM, typename R>
 __device__ __forceinline__ void node_bc(const ProbDev *P, uint8_t fl, long long node, R m, R u[3], bool is_force) {
     if (fl & NF_OBST) {
-        const R *nrm = (const R *)P->nrm;
+        const GLOBAL_AS R *nrm = gmem((const R *)P->nrm);
         R n[3] = {0, 0, 0};
         R un = 0;
 #pragma unroll
@@ -187,8 +239,8 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
 // drawn from splitmix64(seed ^ step<<32 ^ id ^ (a-1)<<56) (reading of the
 // random inflow cell of Sec. 4.1); any other exit is clamped and counted.
 // Returns 1 when the particle was recycled, 2 when clamped, 0 otherwise.
-template <int DIM, typename R>
-__device__ __forceinline__ int advect(const ProbDev *P, R x[3], const R vbar[3], R dt, uint32_t id) {
+template <int DIM, typename R, class PP>
+__device__ __forceinline__ int advect(const PP *P, R x[3], const R vbar[3], R dt, uint32_t id) {
 #pragma unroll
     for (int a = 0; a < DIM; ++a) x[a] = x[a] + dt * vbar[a];
     if (P->face[0][1] == F_OUTFLOW && x[0] >= (R)P->hi[0]) {
@@ -218,8 +270,8 @@ __device__ __forceinline__ int advect(const ProbDev *P, R x[3], const R vbar[3],
 }
 
 // Tile-major cell key of a cell triple.
-template <int DIM>
-__device__ __forceinline__ uint32_t cell_key(const ProbDev *P, const int c[3]) {
+template <int DIM, class PP>
+__device__ __forceinline__ uint32_t cell_key(const PP *P, const int c[3]) {
     constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
     const int tx = c[0] / TX, ty = c[1] / TY, tz = DIM == 3 ? c[2] / TZ : 0;
     const int lx = c[0] - tx * TX, ly = c[1] - ty * TY, lz = DIM == 3 ? c[2] - tz * TZ : 0;
@@ -228,8 +280,8 @@ __device__ __forceinline__ uint32_t cell_key(const ProbDev *P, const int c[3]) {
 }
 
 // Cell triple of a position (the first stencil node of the basis).
-template <int DIM, typename R>
-__device__ __forceinline__ void cell_of(const ProbDev *P, const R x[3], int c[3]) {
+template <int DIM, typename R, class PP>
+__device__ __forceinline__ void cell_of(const PP *P, const R x[3], int c[3]) {
     const R inv_h = (R)P->inv_h;
     c[2] = 0;
 #pragma unroll
@@ -253,7 +305,7 @@ __device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
                                         typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     using A = typename PrecT<PREC>::acc;
-    const A *g = (const A *)P->gA[P->parity];
+    const GLOBAL_AS A *g = gmem((const A *)P->gA[P->parity]);
     const long long NN = P->nnodes;
     const R m = from_acc<PREC>(g[node], P->q_m, flags);
     R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
@@ -262,7 +314,7 @@ __device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
         p[a] = from_acc<PREC>(g[(1 + a) * NN + node], P->q_p, flags);
         I[a] = from_acc<PREC>(g[(1 + DIM + a) * NN + node], P->q_p, flags);
     }
-    const uint8_t fl = P->nflag[node];
+    const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) {
         node_bc<DIM, R>(P, fl, node, m, p, false);
         node_bc<DIM, R>(P, fl, node, m, I, true);
@@ -280,21 +332,22 @@ __device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
                                         typename PrecT<PREC>::real v2[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     using A = typename PrecT<PREC>::acc;
-    const A *gA = (const A *)P->gA[P->parity];
-    const A *gB = (const A *)P->gB[P->parity];
+    const GLOBAL_AS A *gA = gmem((const A *)P->gA[P->parity]);
+    const GLOBAL_AS A *gB = gmem((const A *)P->gB[P->parity]);
     const long long NN = P->nnodes;
     const R m = from_acc<PREC>(gA[node], P->q_m, flags);
     R p[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) p[a] = from_acc<PREC>(gB[a * NN + node], P->q_p, flags);
-    const uint8_t fl = P->nflag[node];
+    const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) node_bc<DIM, R>(P, fl, node, m, p, false);
     const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) v2[a] = p[a] * inv_m;
 }
 
-__device__ __forceinline__ long long node_index(const ProbDev *P, int ix, int iy, int iz) {
+template <class PP>
+__device__ __forceinline__ long long node_index(const PP *P, int ix, int iy, int iz) {
     return (long long)ix + (long long)P->nn[0] * ((long long)iy + (long long)P->nn[1] * iz);
 }
 

@@ -76,6 +76,15 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
     }
 }
 
+// Particles staged in LDS per chunk: what fits in `budget` bytes beside
+// `other` bytes of the kernel's other LDS arrays, in whole blocks.
+constexpr int stage_chunk(int budget, int other, int per_particle) {
+    const int c = (budget - other) / per_particle / kBlock * kBlock;
+    return c < kBlock ? kBlock : (c > 2048 ? 2048 : c);
+}
+constexpr int kStageBudgetS1 = 51200;
+constexpr int kStageBudgetS2 = 40960;
+
 // -------------------------------------------------------------------- S1 --
 // Per-particle factors of S1: x-axis products of the separable stencil sums
 // for mass, momentum and impulse (all in quanta in the fixed-point mode).
@@ -84,36 +93,54 @@ template <int DIM, int SHAPE, typename R> struct S1Factors {
     R mx[W], fx[W], gx[W], px[3][W];
 };
 
-template <int DIM, int SHAPE, int PREC>
-__device__ __forceinline__ void s1_factors(const ProbDev *P, int par, uint32_t k,
+// The S1 inputs of one particle.
+template <typename R> struct S1In {
+    R M, rho, e, v[3], D;    // D = tr G of the previous step
+};
+
+template <int DIM, typename R>
+__device__ __forceinline__ S1In<R> s1_load_global(const ProbDev *P, int par, uint32_t k) {
+    S1In<R> in;
+    in.M = gmem((const R *)P->part[par][PF_M])[k];
+    in.rho = gmem((const R *)P->part[par][PF_RHO])[k];
+    in.e = gmem((const R *)P->part[par][PF_E])[k];
+    in.v[0] = in.v[1] = in.v[2] = 0;
+    in.D = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        in.v[a] = gmem((const R *)P->part[par][PF_V + a])[k];
+        in.D += gmem((const R *)P->part[par][PF_G + a * DIM + a])[k];
+    }
+    return in;
+}
+
+template <int DIM, int SHAPE, int PREC, class PP>
+__device__ __forceinline__ void s1_factors(const PP *P, const S1In<typename PrecT<PREC>::real> &in,
                                            const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
-                                           S1Factors<DIM, SHAPE, typename PrecT<PREC>::real> &f) {
+                                           S1Factors<DIM, SHAPE, typename PrecT<PREC>::real> &f, bool use = true) {
     using R = typename PrecT<PREC>::real;
     constexpr int W = Geo<DIM, SHAPE>::W;
     const R gam = (R)P->gamma, h = (R)P->h;
-    const R M = ((const R *)P->part[par][PF_M])[k];
-    const R rho = ((const R *)P->part[par][PF_RHO])[k];
-    const R e = ((const R *)P->part[par][PF_E])[k];
-    R v[3] = {0, 0, 0}, D = 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        v[a] = ((const R *)P->part[par][PF_V + a])[k];
-        D += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
-    }
+    const R M = in.M, rho = in.rho, e = in.e, D = in.D;
+    const R *v = in.v;
     const R p = eos_p(gam, rho, e);
     const R q = art_visc(P->av_form, (R)P->c0, (R)P->c1, gam, h, rho, p, D);
     const R sm = PrecT<PREC>::fixed ? (R)P->inv_q_m : (R)1;
     const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
-    // M, M v and the impulse dt (P+Q) (M/rho) / h (the 1/h turns d/ds into d/dx)
-    const R Ms = M * sm;
-    const R Fs = (R)P->dt * (p + q) * (M / rho) * (R)P->inv_h * sp;
+    // M, M v and the impulse dt (P+Q) (M/rho) / h (the 1/h turns d/ds into d/dx);
+    // all zero when `use` is false (the particle is summed elsewhere)
+    const R Ms = use ? M * sm : (R)0;
+    const R Fs = use ? (R)P->dt * (p + q) * (M / rho) * (R)P->inv_h * sp : (R)0;
+    R MVs[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) MVs[a] = use ? M * v[a] * sp : (R)0;
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         f.mx[j] = Ms * st.w[0][j];
         f.fx[j] = Fs * st.dw[0][j];
         f.gx[j] = Fs * st.w[0][j];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) f.px[a][j] = (M * v[a] * sp) * st.w[0][j];
+        for (int a = 0; a < DIM; ++a) f.px[a][j] = MVs[a] * st.w[0][j];
     }
 }
 
@@ -125,12 +152,33 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     using A = typename PrecT<PREC>::acc;
     constexpr int NQ = 1 + 2 * DIM;
     constexpr int W = G::W;
+    // Staged particle fields: X[DIM], V[DIM], M, rho, e, diag G[DIM]
+    constexpr int NPF = 3 * DIM + 3;
+    constexpr int CH = stage_chunk(kStageBudgetS1, NQ * G::TN * (int)sizeof(L), NPF * (int)sizeof(R));
+    static_assert(NQ * G::TN * sizeof(L) + NPF * CH * sizeof(R) <= 65536, "S1 LDS");
     __shared__ L tile[NQ * G::TN];
+    __shared__ R spart[NPF * CH];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
     if (!P->active) return;
     const int t = blockIdx.x - wt.start[pi];
+    // Field pointers of the staged particle arrays, read before any store
+    // of the kernel so that they stay uniform (scalar) loads.
+    const GLOBAL_AS R *src[NPF];
+    {
+        const int par0 = P->parity;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            src[a] = gmem((const R *)P->part[par0][PF_X + a]);
+            src[DIM + a] = gmem((const R *)P->part[par0][PF_V + a]);
+            src[2 * DIM + 3 + a] = gmem((const R *)P->part[par0][PF_G + a * DIM + a]);
+        }
+        src[2 * DIM] = gmem((const R *)P->part[par0][PF_M]);
+        src[2 * DIM + 1] = gmem((const R *)P->part[par0][PF_RHO]);
+        src[2 * DIM + 2] = gmem((const R *)P->part[par0][PF_E]);
+    }
+    const View V = make_view(P);
 
     for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) tile[i] = (L)0;
     __syncthreads();
@@ -140,11 +188,11 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
     const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
     const int par = P->parity;
-    const uint32_t *off = P->offs[par];
+    const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
     uint32_t flags = 0;
-    unsigned long long mismatch = 0;
+    uint32_t mismatch = 0;
 
     // Next order: clear this tile's cell histogram and tile total (read by
     // nothing in this sweep, filled by S2).  Next step's grid: clear the
@@ -170,6 +218,36 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
 
+    // The tile's particles are one contiguous range of the sorted order.
+    // They are staged into LDS chunk by chunk with coalesced loads; then
+    // each lane walks the particles of its cell from LDS.
+    const uint32_t tb = off[(uint32_t)t * G::CELLS], te = off[(uint32_t)(t + 1) * G::CELLS];
+#pragma unroll 1
+    for (uint32_t k0 = tb; k0 < te; k0 += CH) {
+        const uint32_t cn = min(te - k0, (uint32_t)CH);
+        __syncthreads();
+        {
+            // all loads of the chunk in flight before the LDS stores; the
+            // index is clamped into the chunk, the stores are guarded
+            constexpr int RB = CH / kBlock;
+            R val[RB][NPF];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t k = k0 + min((uint32_t)(r * kBlock) + threadIdx.x, cn - 1);
+#pragma unroll
+                for (int f = 0; f < NPF; ++f) val[r][f] = src[f][k];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
+                if (i < cn)
+#pragma unroll
+                    for (int f = 0; f < NPF; ++f) spart[f * CH + i] = val[r][f];
+            }
+        }
+        __syncthreads();
+        const uint32_t kb = max(beg, k0), ke = min(end, k0 + cn);
+
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
         L acc[G::WP][NQ];
@@ -179,19 +257,30 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
 
 #pragma unroll 1
-        for (uint32_t k = beg; k < end; ++k) {
+        for (uint32_t k = kb; k < ke; ++k) {
+            const uint32_t i = k - k0;
             R x[3] = {0, 0, 0};
+            S1In<R> in;
+            in.v[0] = in.v[1] = in.v[2] = 0;
+            in.D = 0;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[par][PF_X + a])[k];
-            Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(P, x, st);
-            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (!own) {            // handled after the register sums (rare)
-                if (pass == 0) ++mismatch;
-                continue;
+            for (int a = 0; a < DIM; ++a) {
+                x[a] = spart[a * CH + i];
+                in.v[a] = spart[(DIM + a) * CH + i];
+                in.D += spart[(2 * DIM + 3 + a) * CH + i];
             }
+            in.M = spart[(2 * DIM) * CH + i];
+            in.rho = spart[(2 * DIM + 1) * CH + i];
+            in.e = spart[(2 * DIM + 2) * CH + i];
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(&V, x, st);
+            // A particle whose cell changed between sort and use adds zeros
+            // here (no divergence in the register sums) and is summed by the
+            // deferred loop below (rare).
+            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+            if (pass == 0) mismatch += own ? 0u : 1u;
             S1Factors<DIM, SHAPE, R> f;
-            s1_factors<DIM, SHAPE, PREC>(P, par, k, st, f);
+            s1_factors<DIM, SHAPE, PREC>(&V, in, st, f, own);
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
             const R dwz = DIM == 3 ? st.dw[2][pass] : (R)0;
 #pragma unroll
@@ -211,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                 }
             }
         }
-        if (end > beg) {
+        if (ke > kb) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy)
@@ -224,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                 }
         }
     }
+    }
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
         // contributions go straight to the global grid.
@@ -232,12 +322,12 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R x[3] = {0, 0, 0};
-            for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[par][PF_X + a])[k];
+            for (int a = 0; a < DIM; ++a) x[a] = gmem((const R *)P->part[par][PF_X + a])[k];
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(P, x, st);
             if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
             S1Factors<DIM, SHAPE, R> f;
-            s1_factors<DIM, SHAPE, PREC>(P, par, k, st, f);
+            s1_factors<DIM, SHAPE, PREC>(&V, s1_load_global<DIM, R>(P, par, k), st, f);
 #pragma unroll 1
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll 1
@@ -261,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     __syncthreads();
     flush_tile<DIM, SHAPE, PREC, NQ>(P, c0, tile, (A *)P->gA[par], flags);
     if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
-    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
+    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
 }
 
 // Stage the tile footprint of nodes, interleaved per node:
@@ -382,43 +472,40 @@ template <int DIM> struct DestFoot {
     static constexpr int N = (Tile<DIM>::X + 2) * (Tile<DIM>::Y + 2) * (DIM == 3 ? Tile<DIM>::Z + 2 : 1);
 };
 
-// Cell triple of a tile-major key.
-template <int DIM>
-__device__ __forceinline__ void key_cell(const ProbDev *P, uint32_t key, int c[3]) {
-    constexpr int TX = Tile<DIM>::X, TY = Tile<DIM>::Y, TZ = Tile<DIM>::Z;
-    const uint32_t tile = key / Tile<DIM>::CELLS, l = key % Tile<DIM>::CELLS;
-    const int tx = (int)(tile % (uint32_t)P->ntile[0]);
-    const int ty = (int)((tile / (uint32_t)P->ntile[0]) % (uint32_t)P->ntile[1]);
-    const int tz = DIM == 3 ? (int)(tile / (uint32_t)(P->ntile[0] * P->ntile[1])) : 0;
-    c[0] = tx * TX + (int)(l % TX);
-    c[1] = ty * TY + (int)((l / TX) % TY);
-    c[2] = DIM == 3 ? tz * TZ + (int)(l / (TX * TY)) : 0;
-}
-
+// Rank word of a particle in the next order.  Bit 31 set: bits 0-30 are the
+// rank in the cell's global count.  Clear: bits 21-30 are the destination
+// cell's index in the tile's destination footprint, bits 0-20 the rank among
+// this tile's particles of that cell.
 constexpr uint32_t kRankGlobal = 0x80000000u;
+constexpr int kRankShift = 21;
+constexpr uint32_t kRankMask = (1u << kRankShift) - 1u;
+static_assert(DestFoot<3>::N <= 1024 && DestFoot<2>::N <= 1024, "footprint index must fit 10 bits");
 
 // -------------------------------------------------------------------- S2 --
 // New position of a particle -> its new cell key, and its rank within the
 // cell: from the tile's LDS histogram when the cell lies in the tile's
 // destination footprint (made global by one atomic per cell at the end),
 // else straight from the global histogram (flagged).
-template <int DIM, typename R>
-__device__ __forceinline__ void s2_key_rank(const ProbDev *P, uint32_t k, const R x[3], const R vbar[3],
-                                            R dt, uint32_t id, const int c0[3], uint32_t *hist) {
+template <int DIM, typename R, class PP>
+__device__ __forceinline__ void s2_key_rank(const PP *P, uint32_t *count, uint32_t *ttot, const R x[3],
+                                            const R vbar[3], R dt, uint32_t id, const int c0[3], uint32_t *hist,
+                                            uint32_t &nk, uint32_t &rank, uint32_t &flags) {
     R xn[3] = {x[0], x[1], x[2]};
     advect<DIM, R>(P, xn, vbar, dt, id);
     int cn[3];
     cell_of<DIM, R>(P, xn, cn);
-    const uint32_t nk = cell_key<DIM>(P, cn);
-    P->key[k] = nk;
+    nk = cell_key<DIM>(P, cn);
     const int dl = dest_local<DIM>(c0, cn);
     if (dl >= 0) {
-        P->rank[k] = atomicAdd(&hist[dl], 1u);
+        const uint32_t r = atomicAdd(&hist[dl], 1u);
+        if (r > kRankMask) flags |= ERR_INTERNAL;
+        rank = ((uint32_t)dl << kRankShift) | (r & kRankMask);
     } else {
-        P->rank[k] = atomicAdd(&P->count[nk], 1u) | kRankGlobal;
-        atomicAdd(&P->ttot[nk / Tile<DIM>::CELLS], 1u);
+        rank = atomicAdd(&count[nk], 1u) | kRankGlobal;
+        atomicAdd(&ttot[nk / Tile<DIM>::CELLS], 1u);
     }
 }
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
@@ -429,14 +516,40 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     constexpr int W = G::W;
     constexpr int NF = 2 * DIM;
     constexpr int ND = DestFoot<DIM>::N;
+    // Staged particle fields: X[DIM], V[DIM] (V' after the update), M; and
+    // id (replaced by the new key) and rank
+    constexpr int NPF = 2 * DIM + 1;
+    constexpr int OTHER = NF * G::TN * (int)sizeof(R) + DIM * G::TN * (int)sizeof(L) + (ND + 27) * 4;
+    constexpr int CH = stage_chunk(kStageBudgetS2, OTHER, NPF * (int)sizeof(R) + 8);
+    static_assert(OTHER + CH * (NPF * sizeof(R) + 8) <= 65536, "S2 LDS");
     __shared__ R stage[NF * G::TN];
     __shared__ L tile[DIM * G::TN];
     __shared__ uint32_t hist[ND];
+    __shared__ R spart[NPF * CH];
+    __shared__ uint32_t skey[CH], srank[CH];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
     if (!P->active) return;
     const int t = blockIdx.x - wt.start[pi];
+    // Field pointers, read before any store of the kernel (uniform loads)
+    const GLOBAL_AS R *src[NPF];
+    GLOBAL_AS R *Vg[3];
+    const GLOBAL_AS uint32_t *idg;
+    {
+        const int par0 = P->parity;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            src[a] = gmem((const R *)P->part[par0][PF_X + a]);
+            src[DIM + a] = gmem((const R *)P->part[par0][PF_V + a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Vg[a] = gmem((R *)P->part[par0][PF_V + (a < DIM ? a : 0)]);
+        src[2 * DIM] = gmem((const R *)P->part[par0][PF_M]);
+        idg = gmem((const uint32_t *)P->pid[par0]);
+    }
+    const View V = make_view(P);
+    uint32_t *const cnt_g = P->count, *const ttot_g = P->ttot;
     int c0[3], lc[3];
     tile_cell<DIM>(P, t, c0, lc);
     uint32_t flags = 0;
@@ -449,14 +562,46 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
     const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
     const int par = P->parity;
-    const uint32_t *off = P->offs[par];
+    const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
-    const R *Mp = (const R *)P->part[par][PF_M];
-    const uint32_t *ids = P->pid[par];
-    const R dt = (R)P->dt;
-    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
-    unsigned long long mismatch = 0;
+    const GLOBAL_AS R *Mp = gmem((const R *)P->part[par][PF_M]);
+    const GLOBAL_AS uint32_t *ids = gmem((const uint32_t *)P->pid[par]);
+    const R dt = (R)V.dt;
+    const R sp = PrecT<PREC>::fixed ? (R)V.inv_q_p : (R)1;
+    uint32_t mismatch = 0;
+
+    // Chunks of the tile's particle range staged in LDS (coalesced loads);
+    // V', the new key and rank go back to LDS and are stored coalesced at
+    // the end of the chunk.
+    const uint32_t tb = off[(uint32_t)t * G::CELLS], te = off[(uint32_t)(t + 1) * G::CELLS];
+#pragma unroll 1
+    for (uint32_t k0 = tb; k0 < te; k0 += CH) {
+        const uint32_t cn = min(te - k0, (uint32_t)CH);
+        __syncthreads();
+        {
+            constexpr int RB = CH / kBlock;
+            R val[RB][NPF];
+            uint32_t idv[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t k = k0 + min((uint32_t)(r * kBlock) + threadIdx.x, cn - 1);
+#pragma unroll
+                for (int f = 0; f < NPF; ++f) val[r][f] = src[f][k];
+                idv[r] = idg[k];
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
+                if (i < cn) {
+#pragma unroll
+                    for (int f = 0; f < NPF; ++f) spart[f * CH + i] = val[r][f];
+                    skey[i] = idv[r];
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t kb = max(beg, k0), ke = min(end, k0 + cn);
 
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
@@ -467,20 +612,20 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
 
 #pragma unroll 1
-        for (uint32_t k = beg; k < end; ++k) {
+        for (uint32_t k = kb; k < ke; ++k) {
+            const uint32_t i = k - k0;
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                x[a] = ((const R *)P->part[par][PF_X + a])[k];
-                v[a] = ((const R *)P->part[par][PF_V + a])[k];
+                x[a] = spart[a * CH + i];
+                v[a] = spart[(DIM + a) * CH + i];
             }
             Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(P, x, st);
+            make_stencil<DIM, SHAPE, R>(&V, x, st);
+            // A particle whose cell changed between sort and use adds zeros
+            // here and is handled by the deferred loop below (rare).
             const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (!own) {            // handled after the register sums (rare)
-                if (pass == 0) ++mismatch;
-                continue;
-            }
+            if (pass == 0) mismatch += own ? 0u : 1u;
             if (pass == 0) {
                 // G2P of vstar and of the velocity increment, row by row
                 R vbar[3], dv[3];
@@ -503,18 +648,26 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                         for (int a = 0; a < DIM; ++a) dv[a] += wyz * row[a];
                     }
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    v[a] = v[a] + dv[a];
-                    ((R *)P->part[par][PF_V + a])[k] = v[a];
+                for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
+                if (own) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) spart[(DIM + a) * CH + i] = v[a];
+                    uint32_t nk, rk;
+                    s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, skey[i], c0, hist, nk, rk, flags);
+                    skey[i] = nk;
+                    srank[i] = rk;
+                } else {
+                    skey[i] = kNoKey;      // written by the deferred loop
                 }
-                s2_key_rank<DIM, R>(P, k, x, vbar, dt, ids[k], c0, hist);
             }
-            const R M = Mp[k];
+            const R Ms = own ? spart[(2 * DIM) * CH + i] * sp : (R)0;
             R px[3][W];
 #pragma unroll
-            for (int j = 0; j < W; ++j)
+            for (int a = 0; a < DIM; ++a) {
+                const R mv = own ? Ms * v[a] : (R)0;
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) px[a][j] = (M * v[a] * sp) * st.w[0][j];
+                for (int j = 0; j < W; ++j) px[a][j] = mv * st.w[0][j];
+            }
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
@@ -525,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                     for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_lacc<PREC>(px[a][jx] * wyz);
             }
         }
-        if (end > beg) {
+        if (ke > kb) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy)
@@ -538,6 +691,21 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 }
         }
     }
+        __syncthreads();
+        // coalesced stores of V', key and rank of the chunk
+        GLOBAL_AS uint32_t *keyg = gmem(P->key), *rankg = gmem(P->rank);
+#pragma unroll
+        for (int r = 0; r < CH / kBlock; ++r) {
+            const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
+            if (i < cn && skey[i] != kNoKey) {
+                const uint32_t k = k0 + i;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) Vg[a][k] = spart[(DIM + a) * CH + i];
+                keyg[k] = skey[i];
+                rankg[k] = srank[i];
+            }
+        }
+    }
     if (mismatch) {
         // Particles whose cell changed between sort and use: G2P from the
         // global grid, P2G straight to the global grid.
@@ -547,19 +715,22 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
         for (uint32_t k = beg; k < end; ++k) {
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
             for (int a = 0; a < DIM; ++a) {
-                x[a] = ((const R *)P->part[par][PF_X + a])[k];
-                v[a] = ((const R *)P->part[par][PF_V + a])[k];
+                x[a] = gmem((const R *)P->part[par][PF_X + a])[k];
+                v[a] = gmem((const R *)P->part[par][PF_V + a])[k];
             }
             Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(P, x, st);
+            make_stencil<DIM, SHAPE, R>(&V, x, st);
             if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
             R vbar[3], dv[3], Gd[9];
             g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
             for (int a = 0; a < DIM; ++a) {
                 v[a] = v[a] + dv[a];
-                ((R *)P->part[par][PF_V + a])[k] = v[a];
+                gmem((R *)P->part[par][PF_V + a])[k] = v[a];
             }
-            s2_key_rank<DIM, R>(P, k, x, vbar, dt, ids[k], c0, hist);
+            uint32_t nk, rk;
+            s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, ids[k], c0, hist, nk, rk, flags);
+            gmem(P->key)[k] = nk;
+            gmem(P->rank)[k] = rk;
             const R M = Mp[k];
 #pragma unroll 1
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
@@ -602,9 +773,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
         const long long tile = ((long long)(ttz + dz) * P->ntile[1] + (tty + dy)) * P->ntile[0] + (ttx + dx);
         atomicAdd(&P->ttot[tile], ttl[i]);
     }
-    if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
-    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], mismatch);
-
+    if (flags & (ERR_OVERFLOW | ERR_INTERNAL)) atomicOr((uint32_t *)&P->err, flags & (ERR_OVERFLOW | ERR_INTERNAL));
+    if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
 }
 
 // Wave-level reductions over the 64 lanes of a wavefront.
@@ -853,34 +1023,66 @@ struct S3Sums {
     unsigned long long mis, rec, wall;
 };
 
+// The S3 inputs of one particle, all read at its index in the current order.
+template <typename R> struct S3In {
+    R x[3], v[3], M, rho, e, Dprev;
+    uint32_t id, nk, rk;
+};
+
+template <int DIM, typename R> struct S3Src {
+    const GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *g[3];
+    const GLOBAL_AS uint32_t *id, *key, *rank;
+};
+
+// Destination arrays of S3 (the next parity) and the next cell offsets.
+template <int DIM, typename R> struct S3Dst {
+    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *g[9];
+    GLOBAL_AS uint32_t *id;
+    const GLOBAL_AS uint32_t *noff;
+};
+
+template <int DIM, typename R>
+__device__ __forceinline__ S3In<R> s3_load(const S3Src<DIM, R> &sp, uint32_t k) {
+    S3In<R> in;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { in.x[a] = 0; in.v[a] = 0; }
+    in.Dprev = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        in.x[a] = sp.x[a][k];
+        in.v[a] = sp.v[a][k];
+        in.Dprev += sp.g[a][k];
+    }
+    in.M = sp.M[k];
+    in.rho = sp.rho[k];
+    in.e = sp.e[k];
+    in.id = sp.id[k];
+    in.nk = sp.key[k];
+    in.rk = sp.rank[k];
+    return in;
+}
+
 // The whole particle update of S3 for one particle whose old stencil is st:
 // G2PD / G2P (from the staged footprint, or from the global grid when
 // GLOBAL), energy and density update, move, recycling, scatter into the
 // next sorted order, CFL maxima and FP64 sums.
 template <int DIM, int SHAPE, int PREC, bool GLOBAL>
-__device__ __forceinline__ void s3_particle(ProbDev *P, uint32_t k, const R3<typename PrecT<PREC>::real> &xin,
+__device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, const S3Dst<DIM, typename PrecT<PREC>::real> &dst,
+                                            const S3In<typename PrecT<PREC>::real> &in,
                                             const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
-                                            const int l0[3], const int c0[3],
-                                            const typename PrecT<PREC>::real *stage, const uint32_t *sbase,
+                                            const int l0[3],
+                                            const typename PrecT<PREC>::real *stage, const uint32_t *sfoot,
                                             S3Sums &sums, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
     constexpr int W = G::W;
-    const int par = P->parity, npar = par ^ 1;
-    const R dt = (R)P->dt;
-    const R gam = (R)P->gamma, h = (R)P->h, inv_h = (R)P->inv_h;
+    const R dt = (R)V->dt;
+    const R gam = (R)V->gamma, h = (R)V->h, inv_h = (R)V->inv_h;
 
-    R x[3] = {xin.v[0], xin.v[1], xin.v[2]}, v[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) v[a] = ((const R *)P->part[par][PF_V + a])[k];
-    R M = ((const R *)P->part[par][PF_M])[k];
-    const R rho = ((const R *)P->part[par][PF_RHO])[k];
-    const R e = ((const R *)P->part[par][PF_E])[k];
-    R Dprev = 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) Dprev += ((const R *)P->part[par][PF_G + a * DIM + a])[k];
-    const uint32_t id = P->pid[par][k];
-    const uint32_t nk = P->key[k], rk = P->rank[k];
+    R x[3] = {in.x[0], in.x[1], in.x[2]}, v[3] = {in.v[0], in.v[1], in.v[2]};
+    R M = in.M;
+    const R rho = in.rho, e = in.e, Dprev = in.Dprev;
+    const uint32_t id = in.id, nk = in.nk, rk = in.rk;
 
     R Gm[9];
 #pragma unroll
@@ -924,22 +1126,22 @@ __device__ __forceinline__ void s3_particle(ProbDev *P, uint32_t k, const R3<typ
 #pragma unroll
     for (int a = 0; a < DIM; ++a) D += Gm[a * DIM + a];
     const R p = eos_p(gam, rho, e);
-    const R q = art_visc(P->av_form, (R)P->c0, (R)P->c1, gam, h, rho, p, Dprev);
+    const R q = art_visc(V->av_form, (R)V->c0, (R)V->c1, gam, h, rho, p, Dprev);
     const R J = (R)1 + dt * D;
     if (!(J > (R)0)) flags |= ERR_NONPHYS;
     // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.
-    const double en = (double)e - P->dt * ((double)p + (double)q) * (double)D / (double)rho;
+    const double en = (double)e - V->dt * ((double)p + (double)q) * (double)D / (double)rho;
     R rhon = rho / J;
     R En = (R)en;
 
-    const int mv = advect<DIM, R>(P, x, vbar, dt, id);
+    const int mv = advect<DIM, R>(V, x, vbar, dt, id);
     if (mv == 1) {
         ++sums.rec;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) v[a] = (R)P->inflow_u[a];
-        rhon = (R)P->inflow_rho;
-        En = (R)P->inflow_e;
-        M = (R)P->recycle_mass;
+        for (int a = 0; a < DIM; ++a) v[a] = (R)V->inflow_u[a];
+        rhon = (R)V->inflow_rho;
+        En = (R)V->inflow_e;
+        M = (R)V->recycle_mass;
 #pragma unroll
         for (int c = 0; c < 9; ++c) Gm[c] = 0;
     } else if (mv == 2) {
@@ -947,17 +1149,15 @@ __device__ __forceinline__ void s3_particle(ProbDev *P, uint32_t k, const R3<typ
     }
     if (!isfinite((double)En) || !isfinite((double)rhon)) flags |= ERR_NONFINITE;
 
-    // Slot in the next sorted order: the cell's offset plus the rank.
-    const uint32_t np = (uint32_t)P->np;
-    const uint32_t *noff = P->offs[npar];
+    // Slot in the next sorted order: the cell's offset plus the rank (the
+    // offset plus this tile's base in the cell is staged per footprint cell).
+    const uint32_t np = (uint32_t)V->np;
     uint32_t slot;
     if (rk & kRankGlobal) {
-        slot = noff[nk] + (rk & ~kRankGlobal);
+        slot = dst.noff[nk] + (rk & ~kRankGlobal);
     } else {
-        int cn[3];
-        key_cell<DIM>(P, nk, cn);
-        const int dl = dest_local<DIM>(c0, cn);
-        slot = dl >= 0 ? noff[nk] + sbase[dl] + rk : np;
+        const uint32_t dl = min((rk >> kRankShift) & 1023u, (uint32_t)DestFoot<DIM>::N - 1u);
+        slot = sfoot[dl] + (rk & kRankMask);
     }
     if (slot >= np) {
         flags |= ERR_INTERNAL;
@@ -965,15 +1165,15 @@ __device__ __forceinline__ void s3_particle(ProbDev *P, uint32_t k, const R3<typ
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        ((R *)P->part[npar][PF_X + a])[slot] = x[a];
-        ((R *)P->part[npar][PF_V + a])[slot] = v[a];
+        dst.x[a][slot] = x[a];
+        dst.v[a][slot] = v[a];
     }
-    ((R *)P->part[npar][PF_M])[slot] = M;
-    ((R *)P->part[npar][PF_RHO])[slot] = rhon;
-    ((R *)P->part[npar][PF_E])[slot] = En;
+    dst.M[slot] = M;
+    dst.rho[slot] = rhon;
+    dst.e[slot] = En;
 #pragma unroll
-    for (int c = 0; c < DIM * DIM; ++c) ((R *)P->part[npar][PF_G + c])[slot] = Gm[c];
-    P->pid[npar][slot] = id;
+    for (int c = 0; c < DIM * DIM; ++c) dst.g[c][slot] = Gm[c];
+    dst.id[slot] = id;
 
     // CFL maxima (squared) and FP64 sums of the new state
     double v2 = 0, vb2 = 0;
@@ -998,51 +1198,96 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     constexpr int NF = 2 * DIM;
     constexpr int ND = DestFoot<DIM>::N;
     __shared__ R stage[NF * G::TN];
-    __shared__ uint32_t sbase[ND];
+    __shared__ uint32_t sfoot[ND];
     __shared__ double red[PT_N * (kBlock / 64)];
 
     const int pi = find_prob(wt, blockIdx.x);
     ProbDev *P = wt.prob[pi];
     if (!P->active) return;
     const int t = blockIdx.x - wt.start[pi];
+    // Field pointers, read before any store of the kernel (uniform loads)
+    S3Src<DIM, R> src;
+    {
+        const int par0 = P->parity;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int aa = a < DIM ? a : 0;
+            src.x[a] = gmem((const R *)P->part[par0][PF_X + aa]);
+            src.v[a] = gmem((const R *)P->part[par0][PF_V + aa]);
+            src.g[a] = gmem((const R *)P->part[par0][PF_G + aa * DIM + aa]);
+        }
+        src.M = gmem((const R *)P->part[par0][PF_M]);
+        src.rho = gmem((const R *)P->part[par0][PF_RHO]);
+        src.e = gmem((const R *)P->part[par0][PF_E]);
+        src.id = gmem((const uint32_t *)P->pid[par0]);
+        src.key = gmem((const uint32_t *)P->key);
+        src.rank = gmem((const uint32_t *)P->rank);
+    }
+    S3Dst<DIM, R> dst;
+    {
+        const int np1 = P->parity ^ 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int aa = a < DIM ? a : 0;
+            dst.x[a] = gmem((R *)P->part[np1][PF_X + aa]);
+            dst.v[a] = gmem((R *)P->part[np1][PF_V + aa]);
+        }
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dst.g[c] = gmem((R *)P->part[np1][PF_G + (c < DIM * DIM ? c : 0)]);
+        dst.M = gmem((R *)P->part[np1][PF_M]);
+        dst.rho = gmem((R *)P->part[np1][PF_RHO]);
+        dst.e = gmem((R *)P->part[np1][PF_E]);
+        dst.id = gmem((uint32_t *)P->pid[np1]);
+        dst.noff = gmem((const uint32_t *)P->offs[np1]);
+    }
+    const View V = make_view(P);
     int c0[3], lc[3];
     tile_cell<DIM>(P, t, c0, lc);
     uint32_t flags = 0;
     stage_tile<DIM, SHAPE, PREC, true>(P, c0, stage, flags);
-    const uint32_t *bt = P->basetab + (long long)t * ND;
-    for (int i = threadIdx.x; i < ND; i += kBlock) sbase[i] = bt[i];
+    // Per destination footprint cell: its offset in the next order plus
+    // this tile's base among the cell's particles (only cells that receive
+    // particles from this tile are read).
+    {
+        const GLOBAL_AS uint32_t *bt = gmem((const uint32_t *)P->basetab) + (long long)t * ND;
+        const GLOBAL_AS uint32_t *noff = gmem((const uint32_t *)P->offs[P->parity ^ 1]);
+        for (int i = threadIdx.x; i < ND; i += kBlock) {
+            const int lx = i % (G::TX + 2), ly = (i / (G::TX + 2)) % (G::TY + 2), lz = i / ((G::TX + 2) * (G::TY + 2));
+            const int cn[3] = {c0[0] + lx - 1, c0[1] + ly - 1, DIM == 3 ? c0[2] + lz - 1 : 0};
+            const bool in_dom = cn[0] >= 0 && cn[0] < P->n[0] && cn[1] >= 0 && cn[1] < P->n[1] &&
+                                (DIM == 2 || (cn[2] >= 0 && cn[2] < P->n[2]));
+            sfoot[i] = in_dom ? noff[cell_key<DIM>(P, cn)] + bt[i] : 0u;
+        }
+    }
     __syncthreads();
 
     const int par = P->parity;
-    const uint32_t *off = P->offs[par];
+    const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
     const uint32_t pbeg = off[(uint32_t)t * G::CELLS], pend = off[(uint32_t)(t + 1) * G::CELLS];
     S3Sums sums = {0, 0, 0, {0, 0, 0}, 0, 0, 0, 0, 0};
 
 #pragma unroll 1
     for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
-        R3<R> x = {{0, 0, 0}};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) x.v[a] = ((const R *)P->part[par][PF_X + a])[k];
+        const S3In<R> in = s3_load<DIM, R>(src, k);     // every input in one round trip
         Stencil<DIM, SHAPE, R> st;
-        make_stencil<DIM, SHAPE, R>(P, x.v, st);
+        make_stencil<DIM, SHAPE, R>(&V, in.x, st);
         const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
         const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
                             (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
         if (!inside) { ++sums.mis; continue; }       // handled below (rare)
-        s3_particle<DIM, SHAPE, PREC, false>(P, k, x, st, l0, c0, stage, sbase, sums, flags);
+        s3_particle<DIM, SHAPE, PREC, false>(P, &V, dst, in, st, l0, stage, sfoot, sums, flags);
     }
     if (sums.mis) {
 #pragma unroll 1
         for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
-            R3<R> x = {{0, 0, 0}};
-            for (int a = 0; a < DIM; ++a) x.v[a] = ((const R *)P->part[par][PF_X + a])[k];
+            const S3In<R> in = s3_load<DIM, R>(src, k);
             Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(P, x.v, st);
+            make_stencil<DIM, SHAPE, R>(&V, in.x, st);
             const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
             const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
                                 (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
             if (inside) continue;
-            s3_particle<DIM, SHAPE, PREC, true>(P, k, x, st, l0, c0, stage, sbase, sums, flags);
+            s3_particle<DIM, SHAPE, PREC, true>(P, &V, dst, in, st, l0, stage, sfoot, sums, flags);
         }
     }
 
@@ -1078,11 +1323,11 @@ __global__ __launch_bounds__(kBlock) void k_init_keys(ProbDev *P) {
     const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (k >= P->np) return;
     R x[3] = {0, 0, 0};
-    for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[1][PF_X + a])[k];
+    for (int a = 0; a < DIM; ++a) x[a] = gmem((const R *)P->part[1][PF_X + a])[k];
     int c[3];
     cell_of<DIM, R>(P, x, c);
     const uint32_t nk = cell_key<DIM>(P, c);
-    P->key[k] = nk;
+    gmem(P->key)[k] = nk;
     P->rank[k] = atomicAdd(&P->count[nk], 1u);
 }
 
@@ -1095,7 +1340,7 @@ __global__ __launch_bounds__(kBlock) void k_init_permute(ProbDev *P) {
     if (slot >= (uint32_t)P->np) { atomicOr((uint32_t *)&P->err, ERR_INTERNAL); return; }
     for (int f = 0; f < PF_N; ++f) {
         if (!P->part[1][f]) continue;
-        ((R *)P->part[0][f])[slot] = ((const R *)P->part[1][f])[k];
+        gmem((R *)P->part[0][f])[slot] = gmem((const R *)P->part[1][f])[k];
     }
     P->pid[0][slot] = P->pid[1][k];
 }
@@ -1111,14 +1356,14 @@ __global__ __launch_bounds__(kBlock) void k_init_stats(ProbDev *P) {
     const R gam = (R)P->gamma;
     for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
         double v2 = 0;
-        const R M = ((const R *)P->part[0][PF_M])[k];
+        const R M = gmem((const R *)P->part[0][PF_M])[k];
         for (int a = 0; a < DIM; ++a) {
-            const R va = ((const R *)P->part[0][PF_V + a])[k];
+            const R va = gmem((const R *)P->part[0][PF_V + a])[k];
             v2 += (double)va * (double)va;
             s[1 + a] += (double)M * (double)va;
         }
-        const R rho = ((const R *)P->part[0][PF_RHO])[k];
-        const R e = ((const R *)P->part[0][PF_E])[k];
+        const R rho = gmem((const R *)P->part[0][PF_RHO])[k];
+        const R e = gmem((const R *)P->part[0][PF_E])[k];
         vmax = fmax(vmax, sqrt(v2));
         cmax = fmax(cmax, (double)sound(gam, rho, eos_p(gam, rho, e)));
         s[0] += (double)M;
