@@ -45,15 +45,16 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     return {
         # X, V, M, rho, e, diag G in; m, p, dt f out; cell offsets in
         "p2g": N * (3 * d + 3) * r + ncells * 4 + nnodes * nq * a,
-        # X, V, M in; V, key, rank out; m, p, dt f, flags in; p2 out; offsets in
-        "g2p_p2g": N * ((3 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
+        # X, V, M, id in; rank out; m, p, dt f, flags in; p2 out; offsets in
+        # (V' and the new key are recomputed by the update sweep)
+        "g2p_p2g": N * ((2 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
         # tile totals in, tile bases out
         "tilescan": (ncells // 256) * 8,
         # cell counts in, offsets out
         "cellscan": ncells * 8,
-        # X, V, M, rho, e, diag G, id, key, rank, offset in; X, V, M, rho, e,
-        # G, id out; m, p, dt f, p2, flags in
-        "update": N * ((3 * d + 3) * r + 12 + (2 * d + 3 + d * d) * r + 4 + 4) + nnodes * ((1 + 3 * d) * a + 1),
+        # X, V, M, rho, e, diag G, id, rank in; X, V', M, rho, e, G, id out;
+        # m, p, dt f, p2, flags in
+        "update": N * ((3 * d + 3) * r + 8 + (2 * d + 3 + d * d) * r + 4) + nnodes * ((1 + 3 * d) * a + 1),
         "finalize": 0,
     }
 

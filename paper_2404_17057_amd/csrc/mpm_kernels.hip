@@ -76,15 +76,6 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
     }
 }
 
-// Particles staged in LDS per chunk: what fits in `budget` bytes beside
-// `other` bytes of the kernel's other LDS arrays, in whole blocks.
-constexpr int stage_chunk(int budget, int other, int per_particle) {
-    const int c = (budget - other) / per_particle / kBlock * kBlock;
-    return c < kBlock ? kBlock : (c > 2048 ? 2048 : c);
-}
-constexpr int kStageBudgetS1 = 51200;
-constexpr int kStageBudgetS2 = 40960;
-
 // -------------------------------------------------------------------- S1 --
 // Per-particle factors of S1: x-axis products of the separable stencil sums
 // for mass, momentum and impulse (all in quanta in the fixed-point mode).
@@ -152,12 +143,9 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     using A = typename PrecT<PREC>::acc;
     constexpr int NQ = 1 + 2 * DIM;
     constexpr int W = G::W;
-    // Staged particle fields: X[DIM], V[DIM], M, rho, e, diag G[DIM]
+    // Particle fields read per particle: X[DIM], V[DIM], M, rho, e, diag G[DIM]
     constexpr int NPF = 3 * DIM + 3;
-    constexpr int CH = stage_chunk(kStageBudgetS1, NQ * G::TN * (int)sizeof(L), NPF * (int)sizeof(R));
-    static_assert(NQ * G::TN * sizeof(L) + NPF * CH * sizeof(R) <= 65536, "S1 LDS");
     __shared__ L tile[NQ * G::TN];
-    __shared__ R spart[NPF * CH];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
@@ -218,36 +206,9 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
 
-    // The tile's particles are one contiguous range of the sorted order.
-    // They are staged into LDS chunk by chunk with coalesced loads; then
-    // each lane walks the particles of its cell from LDS.
-    const uint32_t tb = off[(uint32_t)t * G::CELLS], te = off[(uint32_t)(t + 1) * G::CELLS];
-#pragma unroll 1
-    for (uint32_t k0 = tb; k0 < te; k0 += CH) {
-        const uint32_t cn = min(te - k0, (uint32_t)CH);
-        __syncthreads();
-        {
-            // all loads of the chunk in flight before the LDS stores; the
-            // index is clamped into the chunk, the stores are guarded
-            constexpr int RB = CH / kBlock;
-            R val[RB][NPF];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const uint32_t k = k0 + min((uint32_t)(r * kBlock) + threadIdx.x, cn - 1);
-#pragma unroll
-                for (int f = 0; f < NPF; ++f) val[r][f] = src[f][k];
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
-                if (i < cn)
-#pragma unroll
-                    for (int f = 0; f < NPF; ++f) spart[f * CH + i] = val[r][f];
-            }
-        }
-        __syncthreads();
-        const uint32_t kb = max(beg, k0), ke = min(end, k0 + cn);
-
+    // Each lane walks the particles of its cell; the fields of the next
+    // particle are loaded while the current one is summed (the index is
+    // clamped, so the last iteration reloads its own particle).
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
         L acc[G::WP][NQ];
@@ -256,22 +217,28 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
 
+        R cur[NPF];
+#pragma unroll
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? src[f][beg] : (R)0;
 #pragma unroll 1
-        for (uint32_t k = kb; k < ke; ++k) {
-            const uint32_t i = k - k0;
+        for (uint32_t k = beg; k < end; ++k) {
+            R nxt[NPF];
+            const uint32_t kn = min(k + 1, end - 1);
+#pragma unroll
+            for (int f = 0; f < NPF; ++f) nxt[f] = src[f][kn];
             R x[3] = {0, 0, 0};
             S1In<R> in;
             in.v[0] = in.v[1] = in.v[2] = 0;
             in.D = 0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                x[a] = spart[a * CH + i];
-                in.v[a] = spart[(DIM + a) * CH + i];
-                in.D += spart[(2 * DIM + 3 + a) * CH + i];
+                x[a] = cur[a];
+                in.v[a] = cur[DIM + a];
+                in.D += cur[2 * DIM + 3 + a];
             }
-            in.M = spart[(2 * DIM) * CH + i];
-            in.rho = spart[(2 * DIM + 1) * CH + i];
-            in.e = spart[(2 * DIM + 2) * CH + i];
+            in.M = cur[2 * DIM];
+            in.rho = cur[2 * DIM + 1];
+            in.e = cur[2 * DIM + 2];
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(&V, x, st);
             // A particle whose cell changed between sort and use adds zeros
@@ -299,8 +266,10 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                     if constexpr (DIM == 3) ac[3 + DIM] += to_lacc<PREC>(f.gx[jx] * ydz);
                 }
             }
+#pragma unroll
+            for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
         }
-        if (ke > kb) {
+        if (end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy)
@@ -312,7 +281,6 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                         if (acc[jy * W + jx][q] != (L)0) lds_add(&tile[q * G::TN + li], acc[jy * W + jx][q]);
                 }
         }
-    }
     }
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
@@ -354,52 +322,52 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
 }
 
+// Per-node stride of the staged footprint: vstar and dvel (S2), plus v2 (S3).
+template <int DIM, bool WITH_B> constexpr int stage_stride() { return (WITH_B ? 3 : 2) * DIM; }
+
 // Stage the tile footprint of nodes, interleaved per node:
-// lds[li * 2DIM + f]: f < DIM vstar, f >= DIM dvel (S2) or v2 (S3).
+// lds[li * NF + f]: f < DIM vstar, DIM <= f < 2 DIM dvel, 2 DIM <= f v2 (S3).
 template <int DIM, int SHAPE, int PREC, bool WITH_B>
 __device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
                                            typename PrecT<PREC>::real *lds, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
-    constexpr int NF = 2 * DIM;
+    constexpr int NF = stage_stride<DIM, WITH_B>();
 #pragma unroll 1
     for (int li = threadIdx.x; li < G::TN; li += kBlock) {
         const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
         const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
-        R vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+        R vs[3] = {0, 0, 0}, dv[3] = {0, 0, 0}, v2[3] = {0, 0, 0};
         if (gx < P->nn[0] && gy < P->nn[1] && gz < P->nn[2]) {
             const long long node = node_index(P, gx, gy, gz);
-            if constexpr (WITH_B) {
-                R unused[3];
-                stage_A<DIM, PREC>(P, node, vs, unused, flags);
-                stage_B<DIM, PREC>(P, node, dv, flags);
-            } else {
-                stage_A<DIM, PREC>(P, node, vs, dv, flags);
-            }
+            stage_A<DIM, PREC>(P, node, vs, dv, flags);
+            if constexpr (WITH_B) stage_B<DIM, PREC>(P, node, v2, flags);
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             lds[li * NF + a] = vs[a];
             lds[li * NF + DIM + a] = dv[a];
+            if constexpr (WITH_B) lds[li * NF + 2 * DIM + a] = v2[a];
         }
     }
 }
 
 // Staged value f of node (l0 + j) of the footprint.
-template <int DIM, int SHAPE, typename R>
+template <int DIM, int SHAPE, typename R, int NF>
 __device__ __forceinline__ const R *node_ptr(const R *lds, const int l0[3], int jx, int jy, int jz) {
     using G = Geo<DIM, SHAPE>;
-    return lds + (((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx)) * (2 * DIM);
+    return lds + (((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx)) * NF;
 }
 
-// G2P of the staged vstar (fields 0..DIM-1) at one particle, summed row by
-// row: vbar = sum_z,y w_z w_y (sum_x w_x vstar).  S2 and S3 both call this,
-// so the same particle gets the same bits in both sweeps.
-template <int DIM, int SHAPE, typename R>
-__device__ __forceinline__ void g2p_vstar(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3], R vbar[3]) {
+// G2P of one staged vector field (fields OFF..OFF+DIM-1 of the node) at one
+// particle, summed row by row: out = sum_z,y w_z w_y (sum_x w_x f).  S2 and
+// S3 both call this (vstar and dvel), so the same particle gets the same
+// bits in both sweeps.
+template <int DIM, int SHAPE, typename R, int NF, int OFF>
+__device__ __forceinline__ void g2p_field(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3], R out[3]) {
     constexpr int W = Geo<DIM, SHAPE>::W;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vbar[a] = 0;
+    for (int a = 0; a < 3; ++a) out[a] = 0;
 #pragma unroll
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll
@@ -407,42 +375,46 @@ __device__ __forceinline__ void g2p_vstar(const R *lds, const Stencil<DIM, SHAPE
             R row[3] = {0, 0, 0};
 #pragma unroll
             for (int jx = 0; jx < W; ++jx) {
-                const R *nd = node_ptr<DIM, SHAPE, R>(lds, l0, jx, jy, jz);
+                const R *nd = node_ptr<DIM, SHAPE, R, NF>(lds, l0, jx, jy, jz);
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[a];
+                for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[OFF + a];
             }
             const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) vbar[a] += wyz * row[a];
+            for (int a = 0; a < DIM; ++a) out[a] += wyz * row[a];
         }
 }
 
 // The same G2P sums computed from the global grid, for a particle whose
 // stencil leaves the staged footprint: node values from the same staging
-// functions, summed in the same order.  Used only by the deferred loops.
-template <int DIM, int SHAPE, int PREC, bool SECOND_IS_B>
+// functions, summed in the same order.  vbar and dv are the G2P of vstar and
+// dvel; with WITH_G, Gm is the G2PD of v2.  Used only by the deferred loops.
+template <int DIM, int SHAPE, int PREC, bool WITH_G>
 __device__ __forceinline__ void g2p_global(const ProbDev *P, const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
-                                           typename PrecT<PREC>::real vbar[3], typename PrecT<PREC>::real other[3],
+                                           typename PrecT<PREC>::real vbar[3], typename PrecT<PREC>::real dv[3],
                                            typename PrecT<PREC>::real Gm[9], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
     constexpr int W = Geo<DIM, SHAPE>::W;
     const R inv_h = (R)P->inv_h;
-    for (int a = 0; a < 3; ++a) { vbar[a] = 0; other[a] = 0; }
+    for (int a = 0; a < 3; ++a) { vbar[a] = 0; dv[a] = 0; }
     for (int c = 0; c < 9; ++c) Gm[c] = 0;
 #pragma unroll 1
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll 1
         for (int jy = 0; jy < W; ++jy) {
-            R row[3] = {0, 0, 0}, row2[3] = {0, 0, 0}, sx[3] = {0, 0, 0};
+            R row[3] = {0, 0, 0}, rowd[3] = {0, 0, 0}, row2[3] = {0, 0, 0}, sx[3] = {0, 0, 0};
             for (int jx = 0; jx < W; ++jx) {
                 const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
-                R vs[3], f1[3];
-                if constexpr (SECOND_IS_B) { R d[3]; stage_A<DIM, PREC>(P, node, vs, d, flags); stage_B<DIM, PREC>(P, node, f1, flags); }
-                else stage_A<DIM, PREC>(P, node, vs, f1, flags);
+                R vs[3], d[3], v2[3] = {0, 0, 0};
+                stage_A<DIM, PREC>(P, node, vs, d, flags);
+                if constexpr (WITH_G) stage_B<DIM, PREC>(P, node, v2, flags);
                 for (int a = 0; a < DIM; ++a) {
                     row[a] += st.w[0][jx] * vs[a];
-                    row2[a] += st.w[0][jx] * f1[a];
-                    sx[a] += st.dw[0][jx] * f1[a];
+                    rowd[a] += st.w[0][jx] * d[a];
+                    if constexpr (WITH_G) {
+                        row2[a] += st.w[0][jx] * v2[a];
+                        sx[a] += st.dw[0][jx] * v2[a];
+                    }
                 }
             }
             const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
@@ -450,10 +422,12 @@ __device__ __forceinline__ void g2p_global(const ProbDev *P, const Stencil<DIM, 
             const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
             for (int a = 0; a < DIM; ++a) {
                 vbar[a] += wyz * row[a];
-                other[a] += wyz * row2[a];
-                Gm[a * DIM + 0] += wyz * sx[a];
-                Gm[a * DIM + 1] += dyz * row2[a];
-                if (DIM == 3) Gm[a * DIM + 2] += ydz * row2[a];
+                dv[a] += wyz * rowd[a];
+                if constexpr (WITH_G) {
+                    Gm[a * DIM + 0] += wyz * sx[a];
+                    Gm[a * DIM + 1] += dyz * row2[a];
+                    if (DIM == 3) Gm[a * DIM + 2] += ydz * row2[a];
+                }
             }
         }
     for (int c = 0; c < DIM * DIM; ++c) Gm[c] *= inv_h;
@@ -505,7 +479,6 @@ __device__ __forceinline__ void s2_key_rank(const PP *P, uint32_t *count, uint32
         atomicAdd(&ttot[nk / Tile<DIM>::CELLS], 1u);
     }
 }
-constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
@@ -514,19 +487,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     using L = typename PrecT<PREC>::lacc;
     using A = typename PrecT<PREC>::acc;
     constexpr int W = G::W;
-    constexpr int NF = 2 * DIM;
+    constexpr int NF = stage_stride<DIM, false>();
     constexpr int ND = DestFoot<DIM>::N;
-    // Staged particle fields: X[DIM], V[DIM] (V' after the update), M; and
-    // id (replaced by the new key) and rank
+    // Particle fields read per particle: X[DIM], V[DIM], M (and the id)
     constexpr int NPF = 2 * DIM + 1;
-    constexpr int OTHER = NF * G::TN * (int)sizeof(R) + DIM * G::TN * (int)sizeof(L) + (ND + 27) * 4;
-    constexpr int CH = stage_chunk(kStageBudgetS2, OTHER, NPF * (int)sizeof(R) + 8);
-    static_assert(OTHER + CH * (NPF * sizeof(R) + 8) <= 65536, "S2 LDS");
     __shared__ R stage[NF * G::TN];
     __shared__ L tile[DIM * G::TN];
     __shared__ uint32_t hist[ND];
-    __shared__ R spart[NPF * CH];
-    __shared__ uint32_t skey[CH], srank[CH];
 
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
@@ -534,7 +501,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const int t = blockIdx.x - wt.start[pi];
     // Field pointers, read before any store of the kernel (uniform loads)
     const GLOBAL_AS R *src[NPF];
-    GLOBAL_AS R *Vg[3];
     const GLOBAL_AS uint32_t *idg;
     {
         const int par0 = P->parity;
@@ -543,8 +509,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             src[a] = gmem((const R *)P->part[par0][PF_X + a]);
             src[DIM + a] = gmem((const R *)P->part[par0][PF_V + a]);
         }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Vg[a] = gmem((R *)P->part[par0][PF_V + (a < DIM ? a : 0)]);
         src[2 * DIM] = gmem((const R *)P->part[par0][PF_M]);
         idg = gmem((const uint32_t *)P->pid[par0]);
     }
@@ -571,38 +535,9 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const R sp = PrecT<PREC>::fixed ? (R)V.inv_q_p : (R)1;
     uint32_t mismatch = 0;
 
-    // Chunks of the tile's particle range staged in LDS (coalesced loads);
-    // V', the new key and rank go back to LDS and are stored coalesced at
-    // the end of the chunk.
-    const uint32_t tb = off[(uint32_t)t * G::CELLS], te = off[(uint32_t)(t + 1) * G::CELLS];
-#pragma unroll 1
-    for (uint32_t k0 = tb; k0 < te; k0 += CH) {
-        const uint32_t cn = min(te - k0, (uint32_t)CH);
-        __syncthreads();
-        {
-            constexpr int RB = CH / kBlock;
-            R val[RB][NPF];
-            uint32_t idv[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const uint32_t k = k0 + min((uint32_t)(r * kBlock) + threadIdx.x, cn - 1);
-#pragma unroll
-                for (int f = 0; f < NPF; ++f) val[r][f] = src[f][k];
-                idv[r] = idg[k];
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
-                if (i < cn) {
-#pragma unroll
-                    for (int f = 0; f < NPF; ++f) spart[f * CH + i] = val[r][f];
-                    skey[i] = idv[r];
-                }
-            }
-        }
-        __syncthreads();
-        const uint32_t kb = max(beg, k0), ke = min(end, k0 + cn);
-
+    // Each lane walks the particles of its cell, loading the next
+    // particle's fields while the current one is processed.
+    GLOBAL_AS uint32_t *rankg = gmem(P->rank);
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
         L acc[G::WP][DIM];
@@ -611,14 +546,23 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
 
+        R cur[NPF];
+        uint32_t cur_id = 0;
+#pragma unroll
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? src[f][beg] : (R)0;
+        if (end > beg) cur_id = idg[beg];
 #pragma unroll 1
-        for (uint32_t k = kb; k < ke; ++k) {
-            const uint32_t i = k - k0;
+        for (uint32_t k = beg; k < end; ++k) {
+            R nxt[NPF];
+            const uint32_t kn = min(k + 1, end - 1);
+#pragma unroll
+            for (int f = 0; f < NPF; ++f) nxt[f] = src[f][kn];
+            const uint32_t nxt_id = idg[kn];
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                x[a] = spart[a * CH + i];
-                v[a] = spart[(DIM + a) * CH + i];
+                x[a] = cur[a];
+                v[a] = cur[DIM + a];
             }
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(&V, x, st);
@@ -626,41 +570,24 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             // here and is handled by the deferred loop below (rare).
             const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
             if (pass == 0) mismatch += own ? 0u : 1u;
-            if (pass == 0) {
-                // G2P of vstar and of the velocity increment, row by row
-                R vbar[3], dv[3];
-                g2p_vstar<DIM, SHAPE, R>(stage, st, lc, vbar);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) dv[a] = 0;
-#pragma unroll
-                for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
-#pragma unroll
-                    for (int jy = 0; jy < W; ++jy) {
-                        R row[3] = {0, 0, 0};
-#pragma unroll
-                        for (int jx = 0; jx < W; ++jx) {
-                            const R *nd = node_ptr<DIM, SHAPE, R>(stage, lc, jx, jy, jz);
-#pragma unroll
-                            for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[DIM + a];
-                        }
-                        const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) dv[a] += wyz * row[a];
-                    }
+            // G2P of the velocity increment, row by row: V' = V + dv.  V'
+            // is not stored (the update sweep recomputes it from the same
+            // staged values, same bits), so every pass computes it.
+            {
+                R dv[3];
+                g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, lc, dv);
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
-                if (own) {
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) spart[(DIM + a) * CH + i] = v[a];
-                    uint32_t nk, rk;
-                    s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, skey[i], c0, hist, nk, rk, flags);
-                    skey[i] = nk;
-                    srank[i] = rk;
-                } else {
-                    skey[i] = kNoKey;      // written by the deferred loop
-                }
             }
-            const R Ms = own ? spart[(2 * DIM) * CH + i] * sp : (R)0;
+            if (pass == 0 && own) {
+                // G2P of vstar: the move, the new cell key and the rank
+                R vbar[3];
+                g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
+                uint32_t nk, rk;
+                s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, cur_id, c0, hist, nk, rk, flags);
+                rankg[k] = rk;
+            }
+            const R Ms = own ? cur[2 * DIM] * sp : (R)0;
             R px[3][W];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -677,8 +604,11 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_lacc<PREC>(px[a][jx] * wyz);
             }
+#pragma unroll
+            for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
+            cur_id = nxt_id;
         }
-        if (ke > kb) {
+        if (end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy)
@@ -689,21 +619,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                     for (int a = 0; a < DIM; ++a)
                         if (acc[jy * W + jx][a] != (L)0) lds_add(&tile[a * G::TN + li], acc[jy * W + jx][a]);
                 }
-        }
-    }
-        __syncthreads();
-        // coalesced stores of V', key and rank of the chunk
-        GLOBAL_AS uint32_t *keyg = gmem(P->key), *rankg = gmem(P->rank);
-#pragma unroll
-        for (int r = 0; r < CH / kBlock; ++r) {
-            const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
-            if (i < cn && skey[i] != kNoKey) {
-                const uint32_t k = k0 + i;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) Vg[a][k] = spart[(DIM + a) * CH + i];
-                keyg[k] = skey[i];
-                rankg[k] = srank[i];
-            }
         }
     }
     if (mismatch) {
@@ -723,13 +638,9 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
             R vbar[3], dv[3], Gd[9];
             g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
-            for (int a = 0; a < DIM; ++a) {
-                v[a] = v[a] + dv[a];
-                gmem((R *)P->part[par][PF_V + a])[k] = v[a];
-            }
+            for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
             uint32_t nk, rk;
             s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, ids[k], c0, hist, nk, rk, flags);
-            gmem(P->key)[k] = nk;
             gmem(P->rank)[k] = rk;
             const R M = Mp[k];
 #pragma unroll 1
@@ -1026,12 +937,12 @@ struct S3Sums {
 // The S3 inputs of one particle, all read at its index in the current order.
 template <typename R> struct S3In {
     R x[3], v[3], M, rho, e, Dprev;
-    uint32_t id, nk, rk;
+    uint32_t id, rk;
 };
 
 template <int DIM, typename R> struct S3Src {
     const GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *g[3];
-    const GLOBAL_AS uint32_t *id, *key, *rank;
+    const GLOBAL_AS uint32_t *id, *rank;
 };
 
 // Destination arrays of S3 (the next parity) and the next cell offsets.
@@ -1057,7 +968,6 @@ __device__ __forceinline__ S3In<R> s3_load(const S3Src<DIM, R> &sp, uint32_t k) 
     in.rho = sp.rho[k];
     in.e = sp.e[k];
     in.id = sp.id[k];
-    in.nk = sp.key[k];
     in.rk = sp.rank[k];
     return in;
 }
@@ -1082,13 +992,15 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     R x[3] = {in.x[0], in.x[1], in.x[2]}, v[3] = {in.v[0], in.v[1], in.v[2]};
     R M = in.M;
     const R rho = in.rho, e = in.e, Dprev = in.Dprev;
-    const uint32_t id = in.id, nk = in.nk, rk = in.rk;
+    const uint32_t id = in.id, rk = in.rk;
 
     R Gm[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) Gm[c] = 0;
     R vbar[3] = {0, 0, 0};
+    R dv[3] = {0, 0, 0};
     if constexpr (!GLOBAL) {
+        constexpr int NF = stage_stride<DIM, true>();
         // G2PD of v2, summed row by row
 #pragma unroll
         for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
@@ -1097,11 +1009,11 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
                 R row2[3] = {0, 0, 0}, sx[3] = {0, 0, 0};
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx) {
-                    const R *nd = node_ptr<DIM, SHAPE, R>(stage, l0, jx, jy, jz);
+                    const R *nd = node_ptr<DIM, SHAPE, R, NF>(stage, l0, jx, jy, jz);
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) {
-                        row2[a] += st.w[0][jx] * nd[DIM + a];
-                        sx[a] += st.dw[0][jx] * nd[DIM + a];
+                        row2[a] += st.w[0][jx] * nd[2 * DIM + a];
+                        sx[a] += st.dw[0][jx] * nd[2 * DIM + a];
                     }
                 }
                 const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
@@ -1116,11 +1028,14 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
             }
 #pragma unroll
         for (int c = 0; c < DIM * DIM; ++c) Gm[c] *= inv_h;
-        g2p_vstar<DIM, SHAPE, R>(stage, st, l0, vbar);
+        g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, l0, vbar);
+        g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, l0, dv);
     } else {
-        R v2i[3];
-        g2p_global<DIM, SHAPE, PREC, true>(P, st, vbar, v2i, Gm, flags);
+        g2p_global<DIM, SHAPE, PREC, true>(P, st, vbar, dv, Gm, flags);
     }
+    // FLIP velocity update V' = V + dt A, the same bits as in the G2P sweep
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
 
     R D = 0;
 #pragma unroll
@@ -1154,7 +1069,9 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     const uint32_t np = (uint32_t)V->np;
     uint32_t slot;
     if (rk & kRankGlobal) {
-        slot = dst.noff[nk] + (rk & ~kRankGlobal);
+        int cn[3];
+        cell_of<DIM, R>(V, x, cn);
+        slot = dst.noff[cell_key<DIM>(V, cn)] + (rk & ~kRankGlobal);
     } else {
         const uint32_t dl = min((rk >> kRankShift) & 1023u, (uint32_t)DestFoot<DIM>::N - 1u);
         slot = sfoot[dl] + (rk & kRankMask);
@@ -1195,7 +1112,7 @@ template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
-    constexpr int NF = 2 * DIM;
+    constexpr int NF = stage_stride<DIM, true>();
     constexpr int ND = DestFoot<DIM>::N;
     __shared__ R stage[NF * G::TN];
     __shared__ uint32_t sfoot[ND];
@@ -1220,7 +1137,6 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
         src.rho = gmem((const R *)P->part[par0][PF_RHO]);
         src.e = gmem((const R *)P->part[par0][PF_E]);
         src.id = gmem((const uint32_t *)P->pid[par0]);
-        src.key = gmem((const uint32_t *)P->key);
         src.rank = gmem((const uint32_t *)P->rank);
     }
     S3Dst<DIM, R> dst;
