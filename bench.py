@@ -175,6 +175,47 @@ def ablation(args):
     return {"metric": "precision ablation (configs[3])", **out}
 
 
+def blast3d(args):
+    """The 3D spherical blast on the 256^3 grid (2x2x2 particles per cell,
+    134M particles, FP32 state with int64 fixed-point P2G): particle-steps/s
+    over `--blast-steps` steps after `--blast-warmup`, the per-sweep times and
+    the step's algorithmic HBM bytes; optionally the L1 density and pressure
+    error against the oracle on the 64^3 downscale after
+    `--blast-oracle-steps` steps."""
+    import numpy as np
+    from paper_2404_17057_amd import mpm as G
+    from paper_2404_17057_amd import workloads as W
+    pb = W.blast3d(n=args.blast_n, steps=args.blast_steps)
+    log(f"blast3d {args.blast_n}^3: {pb.n_particles} particles")
+    r = time_gpu(pb, G.FP32_FIX64, args.blast_steps, args.blast_warmup, 3)
+    nt = [(args.blast_n + 7) // 8, (args.blast_n + 7) // 8, (args.blast_n + 3) // 4]
+    b = sweep_bytes(pb, r["nodes"], nt[0] * nt[1] * nt[2] * 256, 4, 8)
+    step_bytes = sum(b.values())
+    out = {"workload": f"blast3d_{args.blast_n}^3_ppc8", "particles": pb.n_particles,
+           "steps": args.blast_steps, "warmup": args.blast_warmup,
+           "value": round(r["value"], 1), "unit": "particle-steps/s",
+           "ms_per_step": round(r["ms_per_step"], 4), "sweeps_ms": r["sweeps_ms"],
+           "step_algorithmic_bytes": int(step_bytes),
+           "step_achieved_GBps": round(step_bytes / (r["ms_per_step"] * 1e-3) / 1e9, 1),
+           "counters": r["counters"]}
+    del pb
+    if args.blast_oracle_steps > 0:
+        from oracle import oracle as O
+        small = W.blast3d(n=64, steps=args.blast_oracle_steps)
+        o = O.Oracle(small)
+        o.step(args.blast_oracle_steps)
+        s = G.Simulation(small, G.FP32_FIX64)
+        s.step(args.blast_oracle_steps)
+        l1 = lambda a, ref: float(np.abs(a - ref).sum() / np.abs(ref).sum())
+        out["accuracy_64^3"] = {"steps": args.blast_oracle_steps,
+                                "rel_l1_density": l1(s.field(G.F_RHO), o.particles(O.F_RHO)),
+                                "rel_l1_pressure": l1(s.field(G.F_P), o.particles(O.F_P))}
+        s.close()
+        o.close()
+    log(f"blast3d: {out}")
+    return out
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -198,6 +239,13 @@ def main():
                          "(prints its own JSON line instead of the throughput line)")
     ap.add_argument("--ablation-steps", type=int, default=1000)
     ap.add_argument("--ablation-oracle-steps", type=int, default=10)
+    ap.add_argument("--blast3d", action="store_true",
+                    help="also time the 3D blast (256^3 grid, 134M particles) and report it beside the line")
+    ap.add_argument("--blast-n", type=int, default=256)
+    ap.add_argument("--blast-steps", type=int, default=100)
+    ap.add_argument("--blast-warmup", type=int, default=5)
+    ap.add_argument("--blast-oracle-steps", type=int, default=0,
+                    help="oracle steps of the 64^3 downscale for the accuracy figure (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of 256 MiB (reference for counter scaling)")
     args = ap.parse_args()
@@ -306,6 +354,7 @@ def main():
         "sweeps_ms": sw,
         "accuracy_vs_oracle": accuracy,
         "serving": serving,
+        "blast3d": blast3d(args) if args.blast3d else None,
         "kernel_source_hash": src_hash,
     }
     if args.calibrate_copy:

@@ -719,11 +719,13 @@ __device__ __forceinline__ void block_reduce_partials(double part[PT_N], double 
 #pragma unroll
         for (int q = 0; q < PT_N; ++q) red[q * nw + w] = part[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (w == 0) {
+        // the wave totals, reduced across the lanes of wave 0 (maxima are
+        // >= 0, so 0 is the identity of both operations here)
+#pragma unroll
         for (int q = 0; q < PT_N; ++q) {
-            double r = red[q * nw];
-            for (int i = 1; i < nw; ++i) r = q < 2 ? fmax(r, red[q * nw + i]) : r + red[q * nw + i];
-            part[q] = r;
+            const double r = lane < nw ? red[q * nw + lane] : 0.0;
+            part[q] = q < 2 ? wave_max(r) : wave_sum(r);
         }
     }
     __syncthreads();
