@@ -171,14 +171,16 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) tile[i] = (L)0;
     __syncthreads();
 
-    int c0[3], lc[3];
-    tile_cell<DIM>(P, t, c0, lc);
-    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
-    const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
+    int c0[3], lc0[3];
+    tile_cell<DIM>(P, t, c0, lc0);
+    const bool valid = c0[0] + lc0[0] < P->n[0] && c0[1] + lc0[1] < P->n[1] &&
+                       (DIM == 2 || c0[2] + lc0[2] < P->n[2]);
     const int par = P->parity;
     const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
+    const int *lc = lc0;
+    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
     uint32_t flags = 0;
     uint32_t mismatch = 0;
 
@@ -514,8 +516,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     }
     const View V = make_view(P);
     uint32_t *const cnt_g = P->count, *const ttot_g = P->ttot;
-    int c0[3], lc[3];
-    tile_cell<DIM>(P, t, c0, lc);
+    int c0[3], lc0[3];
+    tile_cell<DIM>(P, t, c0, lc0);
     uint32_t flags = 0;
 
     for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (L)0;
@@ -523,12 +525,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     stage_tile<DIM, SHAPE, PREC, false>(P, c0, stage, flags);
     __syncthreads();
 
-    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
-    const bool valid = cell[0] < P->n[0] && cell[1] < P->n[1] && (DIM == 2 || cell[2] < P->n[2]);
+    const bool valid = c0[0] + lc0[0] < P->n[0] && c0[1] + lc0[1] < P->n[1] &&
+                       (DIM == 2 || c0[2] + lc0[2] < P->n[2]);
     const int par = P->parity;
     const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
     const uint32_t key = (uint32_t)t * G::CELLS + threadIdx.x;
     const uint32_t beg = valid ? off[key] : 0, end = valid ? off[key + 1] : 0;
+    const int *lc = lc0;
+    const int cell[3] = {c0[0] + lc[0], c0[1] + lc[1], c0[2] + lc[2]};
     const GLOBAL_AS R *Mp = gmem((const R *)P->part[par][PF_M]);
     const GLOBAL_AS uint32_t *ids = gmem((const uint32_t *)P->pid[par]);
     const R dt = (R)V.dt;
@@ -734,19 +738,22 @@ __device__ __forceinline__ void block_reduce_partials(double part[PT_N], double 
 // ------------------------------------------------------------------ scan --
 // Exclusive prefix of the cell histogram into offs[parity ^ 1].
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
-    // Hillis-Steele over the 256 thread totals in LDS.
-    sh[threadIdx.x] = v;
+    // Inclusive scans within the four waves, then the wave totals in LDS.
+    constexpr int NW = kBlock / 64;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) sh[w] = incl;
     __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
-        const uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t t = sh[i];
+        base += i < w ? t : 0u;
+        tot += t;
     }
-    total = sh[kBlock - 1];
-    const uint32_t incl = sh[threadIdx.x];
+    total = tot;
     __syncthreads();
-    return incl - v;
+    return base + incl - v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_a(WorkTab wt) {
@@ -883,36 +890,62 @@ __device__ __forceinline__ T block_reduce_max(T v, T *sh) {
 // Next time step from the per-tile maxima of the step just done (Sec. 2.2,
 // CFL; Sec. 3 (xi)-(xii)), time and conserved sums.  Thread 0 of one
 // workgroup per problem holds the reduced partials.
-__device__ void finalize_problem(ProbDev *P, bool advance, const double part[PT_N]) {
+// Time-stepping state of a problem, read in one batch of loads.
+struct StepState {
+    double dt, t, cfl, h, t_end;
+    long long step, steps_left;
+    int parity;
+    uint32_t err;
+};
+
+__device__ __forceinline__ StepState read_step_state(const ProbDev *P) {
+    StepState s;
+    s.dt = P->dt;
+    s.t = P->t;
+    s.cfl = P->cfl;
+    s.h = P->h;
+    s.t_end = P->t_end;
+    s.step = P->step;
+    s.steps_left = P->steps_left;
+    s.parity = P->parity;
+    s.err = P->err;
+    return s;
+}
+
+__device__ void finalize_problem(ProbDev *P, StepState s, bool advance, const double part[PT_N]) {
     const double vmax = sqrt(part[0]);
     const double cmax = sqrt(part[1]);
     if (advance) {
-        P->dt_last = P->dt;
-        P->t = P->t + P->dt;
-        P->step += 1;
-        P->steps_left -= 1;
-        P->parity ^= 1;
+        P->dt_last = s.dt;
+        s.t = s.t + s.dt;
+        P->t = s.t;
+        P->step = s.step + 1;
+        s.steps_left -= 1;
+        P->steps_left = s.steps_left;
+        P->parity = s.parity ^ 1;
     }
-    double dtn = (vmax + cmax > 0.0) ? P->cfl * P->h / (vmax + cmax) : 0.0;
-    if (P->t_end > 0.0) {
-        const double rest = P->t_end - P->t;
+    double dtn = (vmax + cmax > 0.0) ? s.cfl * s.h / (vmax + cmax) : 0.0;
+    if (s.t_end > 0.0) {
+        const double rest = s.t_end - s.t;
         if (rest < dtn) dtn = rest;
         if (dtn < 0.0) dtn = 0.0;
     }
     P->dt = dtn;
     for (int c = 0; c < 6; ++c) P->cons[c] = part[2 + c];
-    P->active = (P->steps_left > 0 && P->err == 0 && dtn > 0.0 &&
-                 (P->t_end <= 0.0 || P->t < P->t_end)) ? 1 : 0;
+    P->active = (s.steps_left > 0 && s.err == 0 && dtn > 0.0 &&
+                 (s.t_end <= 0.0 || s.t < s.t_end)) ? 1 : 0;
 }
 
 // Reduction of the per-tile partials of one problem by one workgroup.
-__device__ __forceinline__ void reduce_tile_partials(const ProbDev *P, double part[PT_N], double *red) {
+__device__ __forceinline__ void reduce_tile_partials(const GLOBAL_AS double *partials, int ntiles, double part[PT_N],
+                                                     double *red) {
 #pragma unroll
     for (int q = 0; q < PT_N; ++q) part[q] = 0.0;
-    for (int t = threadIdx.x; t < P->ntiles; t += blockDim.x)
+#pragma unroll 2
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
 #pragma unroll
         for (int q = 0; q < PT_N; ++q) {
-            const double v = P->partials[(long long)q * P->ntiles + t];
+            const double v = partials[(long long)q * ntiles + t];
             part[q] = q < 2 ? fmax(part[q], v) : part[q] + v;
         }
     block_reduce_partials(part, red);
@@ -923,10 +956,14 @@ constexpr int kWideBlock = 1024;
 __global__ __launch_bounds__(kWideBlock) void k_finalize(WorkTab wt) {
     __shared__ double red[PT_N * (kWideBlock / 64)];
     ProbDev *P = wt.prob[blockIdx.x];
-    if (!P->active) return;
+    // every descriptor read in one batch, before the first store
+    const int active = P->active, ntiles = P->ntiles;
+    const GLOBAL_AS double *partials = gmem((const double *)P->partials);
+    const StepState st = read_step_state(P);
+    if (!active) return;
     double part[PT_N];
-    reduce_tile_partials(P, part, red);
-    if (threadIdx.x == 0) finalize_problem(P, true, part);
+    reduce_tile_partials(partials, ntiles, part, red);
+    if (threadIdx.x == 0) finalize_problem(P, st, true, part);
 }
 
 // -------------------------------------------------------------------- S3 --
@@ -1297,9 +1334,9 @@ __global__ __launch_bounds__(kBlock) void k_init_stats(ProbDev *P) {
 __global__ __launch_bounds__(kWideBlock) void k_init_finalize(ProbDev *P) {
     __shared__ double red[PT_N * (kWideBlock / 64)];
     double part[PT_N];
-    reduce_tile_partials(P, part, red);
+    reduce_tile_partials(gmem((const double *)P->partials), P->ntiles, part, red);
     if (threadIdx.x != 0) return;
-    finalize_problem(P, false, part);
+    finalize_problem(P, read_step_state(P), false, part);
     P->active = 0;
     P->parity = 0;
 }
