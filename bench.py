@@ -132,7 +132,10 @@ def ablation(args):
     from paper_2404_17057_amd import workloads as W
     from oracle import oracle as O
     pb = W.cylinder(nx=512, ny=256, per_axis=4, steps=args.ablation_steps)
-    M0 = float(pb.mass.sum())
+    # reference mass: the particle masses as the state holds them (FP32 in
+    # the FP32 modes), so the drift measures the grid sums, not the rounding
+    # of the inputs
+    M0s = {"fp64": float(pb.mass.sum()), "fp32": float(pb.mass.astype(np.float32).astype(np.float64).sum())}
     o = O.Oracle(pb)
     o.step(args.ablation_oracle_steps)
     rho_o = o.particles(O.F_RHO)
@@ -158,6 +161,7 @@ def ablation(args):
                 s.step(k)
                 done += k
                 if run == 0:
+                    M0 = M0s["fp64" if prec == G.FP64 else "fp32"]
                     drift = max(drift, abs(float(s.grid(G.G_M).sum()) - M0) / M0)
             if run == 1:
                 torch_sync()
