@@ -144,13 +144,43 @@ __device__ __forceinline__ R art_visc(int form, R c0, R c1, R gamma, R h, R rho,
 }
 
 // -------------------------------------------------------- fixed point --
-// One contribution, already scaled to quanta, as a partial-sum term: in the
-// fixed-point precision it is rounded to the nearest whole quantum (ties to
-// even) first, so every partial sum is an integer and exact in FP64.
+// Contributions are scaled to quanta and, in the fixed-point precision,
+// rounded to whole quanta before any addition, so every partial sum is an
+// integer and exact in FP64.
+//
+// A contribution is the product a*b of two real factors (e.g. M w_x and
+// w_y).  In the fixed-point precision the exact product (two FP32 numbers
+// multiply exactly in FP64) is rounded to the nearest whole quantum, ties to
+// even.  fma(a, b, B) with B = +-1.5 * 2^52 computes the product and that
+// rounding in one instruction: for |a b| < 2^51 the result is B + round(a b)
+// exactly, and the rounding depends on a b alone.  A per-cell partial sum
+// takes the terms of successive particles with alternating signs of B, so
+// it holds the exact integer sum, plus B after an odd number of particles;
+// `unbias` removes that at the end.  Every step stays below 2^53 in
+// magnitude, so no addition rounds.
+constexpr double kFixBias = 6755399441055744.0;     // 1.5 * 2^52
+
 template <int PREC>
-__device__ __forceinline__ typename PrecT<PREC>::lacc to_lacc(typename PrecT<PREC>::real y) {
-    if constexpr (PrecT<PREC>::fixed) return (double)rintf(y);
-    else return (typename PrecT<PREC>::lacc)y;
+__device__ __forceinline__ typename PrecT<PREC>::lacc term(typename PrecT<PREC>::real a, typename PrecT<PREC>::real b,
+                                                           double bias) {
+    if constexpr (PrecT<PREC>::fixed) return fma((double)a, (double)b, bias);
+    else return (typename PrecT<PREC>::lacc)(a * b);
+}
+
+// Bias of the n-th particle of a partial sum, and the final correction.
+__device__ __forceinline__ double term_bias(uint32_t n) { return (n & 1u) ? -kFixBias : kFixBias; }
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::lacc unbias(typename PrecT<PREC>::lacc s, uint32_t count) {
+    if constexpr (PrecT<PREC>::fixed) return (count & 1u) ? s - kFixBias : s;
+    else return s;
+}
+
+// One contribution on its own (no running bias): the same integer as term().
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::lacc term_exact(typename PrecT<PREC>::real a,
+                                                                 typename PrecT<PREC>::real b) {
+    if constexpr (PrecT<PREC>::fixed) return fma((double)a, (double)b, kFixBias) - kFixBias;
+    else return (typename PrecT<PREC>::lacc)(a * b);
 }
 
 // Partial sum -> global accumulator word.  Fixed point: the integer-valued
@@ -160,7 +190,9 @@ template <int PREC>
 __device__ __forceinline__ typename PrecT<PREC>::acc lacc_to_acc(typename PrecT<PREC>::lacc v, uint32_t &flags) {
     if constexpr (PrecT<PREC>::fixed) {
         if (!(fabs(v) < 1125899906842624.0)) { flags |= ERR_OVERFLOW; return 0; }
-        return (long long)v;
+        // v is an integer with |v| < 2^50: v + 1.5 * 2^52 is exact and lies in
+        // [2^52, 2^53), where the bit pattern of a double grows by one per unit
+        return __double_as_longlong(v + kFixBias) - __double_as_longlong(kFixBias);
     } else {
         return (typename PrecT<PREC>::acc)v;
     }
@@ -198,6 +230,13 @@ __device__ __forceinline__ void glb_add(long long *p, long long v) {
 }
 __device__ __forceinline__ void glb_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void glb_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+// The same on global-address-space pointers (global, not flat, atomics).
+__device__ __forceinline__ void glb_add(GLOBAL_AS long long *p, long long v) {
+    __hip_atomic_fetch_add((GLOBAL_AS unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void glb_add(GLOBAL_AS double *p, double v) { unsafeAtomicAdd((double *)p, v); }
+__device__ __forceinline__ void glb_add(GLOBAL_AS float *p, float v) { unsafeAtomicAdd((float *)p, v); }
 
 // ------------------------------------------------------------ boundary --
 // Conditions on one nodal vector (Sec. 3 steps (iii), (vii)): obstacle

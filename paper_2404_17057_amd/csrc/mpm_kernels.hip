@@ -51,17 +51,16 @@ __device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], in
     lc[0] = l % TX; lc[1] = (l / TX) % TY; lc[2] = DIM == 3 ? l / (TX * TY) : 0;
 }
 
-// Footprint flush of an LDS partial-sum tile to the global accumulators.
-// Nodes that only this tile's cells reach (local index W-1 .. T-1 on every
-// axis) are stored; the frame shared with neighbouring tiles is added with
-// one atomic per non-zero value (the frame was cleared by k_zero).
+// Footprint flush (per value, q-major).
 template <int DIM, int SHAPE, int PREC, int NQ>
 __device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
                                            const typename PrecT<PREC>::lacc *tile,
                                            typename PrecT<PREC>::acc *g, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using L = typename PrecT<PREC>::lacc;
+    using A = typename PrecT<PREC>::acc;
     const long long NN = P->nnodes;
+    GLOBAL_AS A *gg = gmem(g);
     for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) {
         const int q = i / G::TN, li = i - q * G::TN;
         const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
@@ -70,7 +69,7 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
         const bool own = ix >= G::W - 1 && ix < G::TX && iy >= G::W - 1 && iy < G::TY &&
                          (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
         const L val = tile[i];
-        auto *dst = &g[q * NN + node_index(P, gx, gy, gz)];
+        GLOBAL_AS A *dst = &gg[q * NN + node_index(P, gx, gy, gz)];
         if (own) *dst = lacc_to_acc<PREC>(val, flags);
         else if (val != (L)0) glb_add(dst, lacc_to_acc<PREC>(val, flags));
     }
@@ -188,11 +187,11 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     // nothing in this sweep, filled by S2).  Next step's grid: clear the
     // frame nodes of this tile's footprint in the other buffer (the owned
     // nodes are overwritten by stores).
-    P->count[key] = 0;
-    if (threadIdx.x == 0) P->ttot[t] = 0;
+    gmem(P->count)[key] = 0;
+    if (threadIdx.x == 0) gmem(P->ttot)[t] = 0;
     {
-        A *gAn = (A *)P->gA[par ^ 1];
-        A *gBn = (A *)P->gB[par ^ 1];
+        GLOBAL_AS A *gAn = gmem((A *)P->gA[par ^ 1]);
+        GLOBAL_AS A *gBn = gmem((A *)P->gB[par ^ 1]);
         const long long NN = P->nnodes;
         for (int li = threadIdx.x; li < G::TN; li += kBlock) {
             const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
@@ -252,6 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             s1_factors<DIM, SHAPE, PREC>(&V, in, st, f, own);
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
             const R dwz = DIM == 3 ? st.dw[2][pass] : (R)0;
+            const double bias = term_bias(k - beg);
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
                 const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
@@ -260,12 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx) {
                     L *ac = acc[jy * W + jx];
-                    ac[0] += to_lacc<PREC>(f.mx[jx] * wyz);
+                    ac[0] += term<PREC>(f.mx[jx], wyz, bias);
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) ac[1 + a] += to_lacc<PREC>(f.px[a][jx] * wyz);
-                    ac[1 + DIM] += to_lacc<PREC>(f.fx[jx] * wyz);
-                    ac[2 + DIM] += to_lacc<PREC>(f.gx[jx] * dyz);
-                    if constexpr (DIM == 3) ac[3 + DIM] += to_lacc<PREC>(f.gx[jx] * ydz);
+                    for (int a = 0; a < DIM; ++a) ac[1 + a] += term<PREC>(f.px[a][jx], wyz, bias);
+                    ac[1 + DIM] += term<PREC>(f.fx[jx], wyz, bias);
+                    ac[2 + DIM] += term<PREC>(f.gx[jx], dyz, bias);
+                    if constexpr (DIM == 3) ac[3 + DIM] += term<PREC>(f.gx[jx], ydz, bias);
                 }
             }
 #pragma unroll
@@ -279,15 +279,17 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                 for (int jx = 0; jx < W; ++jx) {
                     const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (acc[jy * W + jx][q] != (L)0) lds_add(&tile[q * G::TN + li], acc[jy * W + jx][q]);
+                    for (int q = 0; q < NQ; ++q) {
+                        const L v = unbias<PREC>(acc[jy * W + jx][q], end - beg);
+                        if (v != (L)0) lds_add(&tile[q * G::TN + li], v);
+                    }
                 }
         }
     }
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
         // contributions go straight to the global grid.
-        A *g = (A *)P->gA[par];
+        GLOBAL_AS A *g = gmem((A *)P->gA[par]);
         const long long NN = P->nnodes;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
@@ -307,13 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                     const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
                     for (int jx = 0; jx < W; ++jx) {
                         const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
-                        glb_add(&g[node], lacc_to_acc<PREC>(to_lacc<PREC>(f.mx[jx] * wyz), flags));
+                        glb_add(&g[node], lacc_to_acc<PREC>(term_exact<PREC>(f.mx[jx], wyz), flags));
                         for (int a = 0; a < DIM; ++a)
-                            glb_add(&g[(1 + a) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.px[a][jx] * wyz), flags));
-                        glb_add(&g[(1 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.fx[jx] * wyz), flags));
-                        glb_add(&g[(2 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.gx[jx] * dyz), flags));
+                            glb_add(&g[(1 + a) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.px[a][jx], wyz), flags));
+                        glb_add(&g[(1 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.fx[jx], wyz), flags));
+                        glb_add(&g[(2 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.gx[jx], dyz), flags));
                         if (DIM == 3)
-                            glb_add(&g[(3 + DIM) * NN + node], lacc_to_acc<PREC>(to_lacc<PREC>(f.gx[jx] * ydz), flags));
+                            glb_add(&g[(3 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.gx[jx], ydz), flags));
                     }
                 }
         }
@@ -463,7 +465,7 @@ static_assert(DestFoot<3>::N <= 1024 && DestFoot<2>::N <= 1024, "footprint index
 // destination footprint (made global by one atomic per cell at the end),
 // else straight from the global histogram (flagged).
 template <int DIM, typename R, class PP>
-__device__ __forceinline__ void s2_key_rank(const PP *P, uint32_t *count, uint32_t *ttot, const R x[3],
+__device__ __forceinline__ void s2_key_rank(const PP *P, GLOBAL_AS uint32_t *count, GLOBAL_AS uint32_t *ttot, const R x[3],
                                             const R vbar[3], R dt, uint32_t id, const int c0[3], uint32_t *hist,
                                             uint32_t &nk, uint32_t &rank, uint32_t &flags) {
     R xn[3] = {x[0], x[1], x[2]};
@@ -477,8 +479,8 @@ __device__ __forceinline__ void s2_key_rank(const PP *P, uint32_t *count, uint32
         if (r > kRankMask) flags |= ERR_INTERNAL;
         rank = ((uint32_t)dl << kRankShift) | (r & kRankMask);
     } else {
-        rank = atomicAdd(&count[nk], 1u) | kRankGlobal;
-        atomicAdd(&ttot[nk / Tile<DIM>::CELLS], 1u);
+        rank = __hip_atomic_fetch_add(&count[nk], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) | kRankGlobal;
+        __hip_atomic_fetch_add(&ttot[nk / Tile<DIM>::CELLS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
         idg = gmem((const uint32_t *)P->pid[par0]);
     }
     const View V = make_view(P);
-    uint32_t *const cnt_g = P->count, *const ttot_g = P->ttot;
+    GLOBAL_AS uint32_t *const cnt_g = gmem(P->count), *const ttot_g = gmem(P->ttot);
     int c0[3], lc0[3];
     tile_cell<DIM>(P, t, c0, lc0);
     uint32_t flags = 0;
@@ -600,13 +602,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 for (int j = 0; j < W; ++j) px[a][j] = mv * st.w[0][j];
             }
             const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
+            const double bias = term_bias(k - beg);
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
                 const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
 #pragma unroll
                 for (int jx = 0; jx < W; ++jx)
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += to_lacc<PREC>(px[a][jx] * wyz);
+                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += term<PREC>(px[a][jx], wyz, bias);
             }
 #pragma unroll
             for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
@@ -620,15 +623,17 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 for (int jx = 0; jx < W; ++jx) {
                     const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a)
-                        if (acc[jy * W + jx][a] != (L)0) lds_add(&tile[a * G::TN + li], acc[jy * W + jx][a]);
+                    for (int a = 0; a < DIM; ++a) {
+                        const L v = unbias<PREC>(acc[jy * W + jx][a], end - beg);
+                        if (v != (L)0) lds_add(&tile[a * G::TN + li], v);
+                    }
                 }
         }
     }
     if (mismatch) {
         // Particles whose cell changed between sort and use: G2P from the
         // global grid, P2G straight to the global grid.
-        A *g = (A *)P->gB[par];
+        GLOBAL_AS A *g = gmem((A *)P->gB[par]);
         const long long NN = P->nnodes;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
@@ -646,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             uint32_t nk, rk;
             s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, ids[k], c0, hist, nk, rk, flags);
             gmem(P->rank)[k] = rk;
-            const R M = Mp[k];
+            const R Ms = Mp[k] * sp;
 #pragma unroll 1
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll 1
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                         const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
                         for (int a = 0; a < DIM; ++a)
                             glb_add(&g[a * NN + node],
-                                    lacc_to_acc<PREC>(to_lacc<PREC>((M * v[a] * sp) * st.w[0][jx] * wyz), flags));
+                                    lacc_to_acc<PREC>(term_exact<PREC>((Ms * v[a]) * st.w[0][jx], wyz), flags));
                     }
         }
     }
@@ -668,14 +673,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     // tile's particles of that cell get the ranks base .. base + hist - 1.
     // Tile totals are gathered per destination tile (the tile and its
     // neighbours) before going global.
-    uint32_t *bt = P->basetab + (long long)t * ND;
+    GLOBAL_AS uint32_t *bt = gmem(P->basetab) + (long long)t * ND;
     const int ttx = c0[0] / G::TX, tty = c0[1] / G::TY, ttz = c0[2] / G::TZ;
     for (int i = threadIdx.x; i < ND; i += kBlock) {
         const uint32_t cnt = hist[i];
         if (!cnt) continue;
         const int lx = i % (G::TX + 2), ly = (i / (G::TX + 2)) % (G::TY + 2), lz = i / ((G::TX + 2) * (G::TY + 2));
         const int cn[3] = {c0[0] + lx - 1, c0[1] + ly - 1, DIM == 3 ? c0[2] + lz - 1 : 0};
-        bt[i] = atomicAdd(&P->count[cell_key<DIM>(P, cn)], cnt);
+        bt[i] = __hip_atomic_fetch_add(&cnt_g[cell_key<DIM>(P, cn)], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int dx = (cn[0] >= c0[0] + G::TX) - (cn[0] < c0[0]);
         const int dy = (cn[1] >= c0[1] + G::TY) - (cn[1] < c0[1]);
         const int dz = DIM == 3 ? (cn[2] >= c0[2] + G::TZ) - (cn[2] < c0[2]) : 0;
@@ -686,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
         const int i = threadIdx.x;
         const int dx = i % 3 - 1, dy = (i / 3) % 3 - 1, dz = i / 9 - 1;
         const long long tile = ((long long)(ttz + dz) * P->ntile[1] + (tty + dy)) * P->ntile[0] + (ttx + dx);
-        atomicAdd(&P->ttot[tile], ttl[i]);
+        __hip_atomic_fetch_add(&ttot_g[tile], ttl[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (flags & (ERR_OVERFLOW | ERR_INTERNAL)) atomicOr((uint32_t *)&P->err, flags & (ERR_OVERFLOW | ERR_INTERNAL));
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
@@ -1252,7 +1257,7 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     block_reduce_partials(part, red);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < PT_N; ++q) P->partials[(long long)q * P->ntiles + t] = part[q];
+        for (int q = 0; q < PT_N; ++q) gmem(P->partials)[(long long)q * P->ntiles + t] = part[q];
     const uint32_t errs = flags & (ERR_NONPHYS | ERR_NONFINITE | ERR_OVERFLOW | ERR_INTERNAL);
     if (errs) atomicOr((uint32_t *)&P->err, errs);
     if (sums.mis) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], sums.mis);
