@@ -283,3 +283,24 @@ def test_q1_sod_bounded_run_fp64_and_fix():
         assert st["rc"] == 0 and st["step"] == nst
         assert rel_l1(s.field(G.F_RHO), o.particles(O.F_RHO)) <= tol, prec
         assert st["conserved"][0] == pytest.approx(pb.mass.sum(), rel=1e-12 if prec == G.FP64 else 1e-6)
+
+
+@pytest.mark.parametrize("shape", [W.Q1, W.B2])
+def test_paper_sod_full_run(shape):
+    """The paper's Sod tube (100 cells, 2x2 regular lattice, t = 0.143) run to
+    the end: FP64 within 1e-6 and FP32 fixed point within 1e-3 relative L1
+    of the oracle's density (at this size a 1e-7 perturbation of the initial
+    positions grows to 5e-5 by the end with Q1, 1e-7 with B2)."""
+    _gpu()
+    pb = W.sod(nx=100, ny=2, per_axis=2, jitter=0.0, shape=shape, t_end=0.143)
+    o = O.Oracle(pb)
+    assert o.step(0) == 0
+    ref = o.particles(O.F_RHO)
+    for prec, tol in [(G.FP64, 1e-6), (G.FP32_FIX64, 1e-3)]:
+        s = G.Simulation(pb, prec)
+        s.step(0)
+        st = s.status()
+        assert st["rc"] == 0 and st["t"] == 0.143
+        if prec == G.FP64:
+            assert st["step"] == o.status()["step"]
+        assert rel_l1(s.field(G.F_RHO), ref) <= tol, (shape, prec)
