@@ -38,7 +38,7 @@ struct Layout {
     size_t real_sz, acc_sz;
     // byte offsets
     size_t off_prob, off_part[2][PF_N], off_pid[2], off_key, off_rank, off_basetab;
-    size_t off_gA[2], off_gB[2], off_count, off_ttot, off_tbase, off_zero_end, off_offs[2], off_blocksum,
+    size_t off_gA[2], off_gB[2], off_haloA, off_haloB, off_count, off_ttot, off_tbase, off_zero_end, off_offs[2], off_blocksum,
         off_nflag, off_nrm, off_partials, total;
     int has_obstacle;
 };
@@ -119,6 +119,13 @@ Layout make_layout(const mpm_desc *d) {
     for (int p = 0; p < 2; ++p) {
         L.off_gA[p] = o; o = align_up(o + (size_t)(1 + 2 * d->dim) * L.nnodes * L.acc_sz);
         L.off_gB[p] = o; o = align_up(o + (size_t)d->dim * L.nnodes * L.acc_sz);
+    }
+    L.off_haloA = L.off_haloB = (size_t)-1;
+    if (d->dim == 2) {
+        // per tile, the frame nodes of its footprint (4 (W-1) T of them)
+        const size_t nfr = (size_t)4 * (d->shape == MPM_B2 ? 2 : 1) * Tile<2>::X;
+        L.off_haloA = o; o = align_up(o + (size_t)(1 + 2 * d->dim) * L.ntiles * nfr * L.acc_sz);
+        L.off_haloB = o; o = align_up(o + (size_t)d->dim * L.ntiles * nfr * L.acc_sz);
     }
     L.off_count = o; o = align_up(o + (size_t)L.ncells_pad * 4);
     L.off_ttot = o; o = align_up(o + (size_t)L.ntiles * 4);
@@ -312,6 +319,8 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
     P.nflag = (uint8_t *)(H->ws + L.off_nflag);
     P.nrm = H->ws + L.off_nrm;
     P.partials = (double *)(H->ws + L.off_partials);
+    P.haloA = L.off_haloA == (size_t)-1 ? nullptr : (void *)(H->ws + L.off_haloA);
+    P.haloB = L.off_haloB == (size_t)-1 ? nullptr : (void *)(H->ws + L.off_haloB);
     P.parity = 1;      // the unsorted input goes to parity 1, the sort writes parity 0
     P.active = 1;
 

@@ -91,6 +91,8 @@ struct ProbDev {
     uint32_t *tbase;          // exclusive prefix of ttot (ntiles + 1)
     void *gA[2];              // per step parity: m, p[d], I[d]: (1 + 2 dim) * nnodes acc words
     void *gB[2];              // per step parity: p2[d]: dim * nnodes acc words
+    void *haloA, *haloB;      // 2D: per tile, the frame-node partial sums of S1 (NQ per node)
+                              // and of the P2G of S2 (dim per node), q-major; null in 3D
     double *partials;         // PT_N * ntiles, q-major
     uint8_t *nflag;
     void *nrm;                // dim * nnodes real, or null

@@ -339,19 +339,16 @@ __device__ __forceinline__ void cell_of(const PP *P, const R x[3], int c[3]) {
 //   v2    = p2/m       with p2 after the momentum conditions
 // Nodes without mass give 0.
 template <int DIM, int PREC>
-__device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
-                                        typename PrecT<PREC>::real vstar[3],
-                                        typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
+__device__ __forceinline__ void stage_A_raw(const ProbDev *P, long long node, const typename PrecT<PREC>::acc raw[1 + 2 * DIM],
+                                            typename PrecT<PREC>::real vstar[3],
+                                            typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
-    using A = typename PrecT<PREC>::acc;
-    const GLOBAL_AS A *g = gmem((const A *)P->gA[P->parity]);
-    const long long NN = P->nnodes;
-    const R m = from_acc<PREC>(g[node], P->q_m, flags);
+    const R m = from_acc<PREC>(raw[0], P->q_m, flags);
     R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        p[a] = from_acc<PREC>(g[(1 + a) * NN + node], P->q_p, flags);
-        I[a] = from_acc<PREC>(g[(1 + DIM + a) * NN + node], P->q_p, flags);
+        p[a] = from_acc<PREC>(raw[1 + a], P->q_p, flags);
+        I[a] = from_acc<PREC>(raw[1 + DIM + a], P->q_p, flags);
     }
     const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) {
@@ -364,6 +361,19 @@ __device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
         vstar[a] = (p[a] + I[a]) * inv_m;
         dvel[a] = I[a] * inv_m;
     }
+}
+
+template <int DIM, int PREC>
+__device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
+                                        typename PrecT<PREC>::real vstar[3],
+                                        typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
+    using A = typename PrecT<PREC>::acc;
+    const GLOBAL_AS A *g = gmem((const A *)P->gA[P->parity]);
+    const long long NN = P->nnodes;
+    A raw[1 + 2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 1 + 2 * DIM; ++q) raw[q] = g[q * NN + node];
+    stage_A_raw<DIM, PREC>(P, node, raw, vstar, dvel, flags);
 }
 
 template <int DIM, int PREC>
@@ -388,6 +398,105 @@ __device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
 template <class PP>
 __device__ __forceinline__ long long node_index(const PP *P, int ix, int iy, int iz) {
     return (long long)ix + (long long)P->nn[0] * ((long long)iy + (long long)P->nn[1] * iz);
+}
+
+// ---------------------------------------------------------- frame halos --
+// 2D: the footprint of a tile (NX x NX nodes, NX = T + W - 1) holds the
+// nodes that only its own cells reach (local index W-1 .. T-1 on both axes,
+// "owned") and a frame shared with the neighbouring tiles.  The P2G sweeps
+// store the owned sums into the grid and the frame sums into the tile's
+// halo record instead of adding them atomically; a frame node's value is the
+// sum over the 1-4 tiles whose footprint holds it, always in the same order.
+template <int SHAPE> struct Frame2 {
+    static constexpr int T = Tile<2>::X;                 // tiles are square in 2D
+    static constexpr int E = SHAPE == S_B2 ? 2 : 1;      // W - 1
+    static constexpr int NX = T + E;
+    static constexpr int NFR = 4 * E * T;                // frame nodes per tile
+};
+static_assert(Tile<2>::X == Tile<2>::Y, "square 2D tiles");
+
+// Slot of frame position (lx, ly) in a tile's halo record.
+template <int SHAPE> __device__ __forceinline__ int frame_slot(int lx, int ly) {
+    using F = Frame2<SHAPE>;
+    if (ly < F::E) return ly * F::NX + lx;
+    if (ly >= F::T) return F::E * F::NX + (ly - F::T) * F::NX + lx;
+    return 2 * F::E * F::NX + (ly - F::E) * 2 * F::E + (lx < F::E ? lx : lx - F::T + F::E);
+}
+
+// Frame position of halo slot sl (the inverse of frame_slot).
+template <int SHAPE> __device__ __forceinline__ void frame_pos(int sl, int &lx, int &ly) {
+    using F = Frame2<SHAPE>;
+    if (sl < 2 * F::E * F::NX) {
+        const int r = sl / F::NX;
+        ly = r < F::E ? r : r - F::E + F::T;
+        lx = sl % F::NX;
+        return;
+    }
+    sl -= 2 * F::E * F::NX;
+    ly = F::E + sl / (2 * F::E);
+    const int c = sl % (2 * F::E);
+    lx = c < F::E ? c : c - F::E + F::T;
+}
+
+// Tiles along one axis whose footprint holds node g, with g's local index
+// in each.  The first is the node's reducer tile.
+template <int SHAPE> __device__ __forceinline__ int frame_contrib(int g, int ntile, int t[2], int l[2]) {
+    using F = Frame2<SHAPE>;
+    int t1 = g / F::T;
+    if (t1 > ntile - 1) t1 = ntile - 1;
+    t[0] = t1;
+    l[0] = g - t1 * F::T;
+    t[1] = t1;
+    l[1] = l[0];
+    if (l[0] < F::E && t1 > 0) {
+        t[1] = t1 - 1;
+        l[1] = l[0] + F::T;
+        return 2;
+    }
+    return 1;
+}
+
+// Raw accumulators q < NQ of node (gx, gy): the grid value of a node owned
+// by one tile, else the sum of the halo entries of the tiles holding it.
+// All candidate entries are loaded at once (a missing second tile re-reads
+// the first entry, which for a frame node is always a frame position, and
+// is masked out), then summed in a fixed order.  Returns true for a frame
+// node.
+template <int SHAPE, int NQ, typename A>
+__device__ __forceinline__ bool gather_raw(const ProbDev *P, const GLOBAL_AS A *grid, const GLOBAL_AS A *halo,
+                                           long long node, int gx, int gy, A out[NQ]) {
+    using F = Frame2<SHAPE>;
+    int tx[2], lx[2], ty[2], ly[2];
+    const int cx = frame_contrib<SHAPE>(gx, P->ntile[0], tx, lx);
+    const int cy = frame_contrib<SHAPE>(gy, P->ntile[1], ty, ly);
+    if (cx == 1 && cy == 1 && lx[0] >= F::E && lx[0] < F::T && ly[0] >= F::E && ly[0] < F::T) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = grid[q * P->nnodes + node];
+        return false;
+    }
+    const long long ntl = P->ntiles;
+    long long base[4];
+    bool use[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int i = c >> 1, j = c & 1;
+        use[c] = i < cx && j < cy;
+        const int ii = use[c] ? i : 0, jj = use[c] ? j : 0;
+        base[c] = ((long long)ty[jj] * P->ntile[0] + tx[ii]) * F::NFR + frame_slot<SHAPE>(lx[ii], ly[jj]);
+    }
+    A v[4][NQ];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[c][q] = halo[(long long)q * ntl * F::NFR + base[c]];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        A sum = (A)0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sum += use[c] ? v[c][q] : (A)0;
+        out[q] = sum;
+    }
+    return true;
 }
 
 // Problem owning workgroup b of a batched launch.

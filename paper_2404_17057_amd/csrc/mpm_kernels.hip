@@ -51,11 +51,19 @@ __device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], in
     lc[0] = l % TX; lc[1] = (l / TX) % TY; lc[2] = DIM == 3 ? l / (TX * TY) : 0;
 }
 
-// Footprint flush (per value, q-major).
+// Footprint flush of an LDS partial-sum tile, one value per thread and
+// pass (q-major).  Nodes that only this tile's cells reach (local index
+// W-1 .. T-1 on every axis) are stored into the grid.  The frame shared with
+// neighbouring tiles goes, in 2D, into this tile's halo record (plain
+// stores; the readers sum the records of the tiles holding a node), and in
+// 3D is added to the grid with one atomic per non-zero value (the frame was
+// cleared the step before).
+template <int DIM> constexpr bool kHalo = DIM == 2;
+
 template <int DIM, int SHAPE, int PREC, int NQ>
-__device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
+__device__ __forceinline__ void flush_tile(const ProbDev *P, int t, const int c0[3],
                                            const typename PrecT<PREC>::lacc *tile,
-                                           typename PrecT<PREC>::acc *g, uint32_t &flags) {
+                                           typename PrecT<PREC>::acc *g, void *halo, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using L = typename PrecT<PREC>::lacc;
     using A = typename PrecT<PREC>::acc;
@@ -69,9 +77,15 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, const int c0[3],
         const bool own = ix >= G::W - 1 && ix < G::TX && iy >= G::W - 1 && iy < G::TY &&
                          (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
         const L val = tile[i];
-        GLOBAL_AS A *dst = &gg[q * NN + node_index(P, gx, gy, gz)];
-        if (own) *dst = lacc_to_acc<PREC>(val, flags);
-        else if (val != (L)0) glb_add(dst, lacc_to_acc<PREC>(val, flags));
+        if (own) {
+            gg[q * NN + node_index(P, gx, gy, gz)] = lacc_to_acc<PREC>(val, flags);
+        } else if constexpr (kHalo<DIM>) {
+            GLOBAL_AS A *h = gmem((A *)halo);
+            h[((long long)q * P->ntiles + t) * Frame2<SHAPE>::NFR + frame_slot<SHAPE>(ix, iy)] =
+                lacc_to_acc<PREC>(val, flags);
+        } else if (val != (L)0) {
+            glb_add(&gg[q * NN + node_index(P, gx, gy, gz)], lacc_to_acc<PREC>(val, flags));
+        }
     }
 }
 
@@ -184,12 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     uint32_t mismatch = 0;
 
     // Next order: clear this tile's cell histogram and tile total (read by
-    // nothing in this sweep, filled by S2).  Next step's grid: clear the
-    // frame nodes of this tile's footprint in the other buffer (the owned
-    // nodes are overwritten by stores).
+    // nothing in this sweep, filled by S2).  3D, next step's grid: clear the
+    // frame nodes of this tile's footprint in the other buffer, which the
+    // flush adds to atomically (the owned nodes are overwritten by stores;
+    // in 2D the frame sums go through the halo records instead).
     gmem(P->count)[key] = 0;
     if (threadIdx.x == 0) gmem(P->ttot)[t] = 0;
-    {
+    if constexpr (!kHalo<DIM>) {
         GLOBAL_AS A *gAn = gmem((A *)P->gA[par ^ 1]);
         GLOBAL_AS A *gBn = gmem((A *)P->gB[par ^ 1]);
         const long long NN = P->nnodes;
@@ -288,9 +303,8 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     }
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
-        // contributions go straight to the global grid.
-        GLOBAL_AS A *g = gmem((A *)P->gA[par]);
-        const long long NN = P->nnodes;
+        // contributions go one by one into the LDS tile (their cell must
+        // still lie in this tile).
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R x[3] = {0, 0, 0};
@@ -298,6 +312,12 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(P, x, st);
             if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
+            const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+            if (l0[0] < 0 || l0[0] >= G::TX || l0[1] < 0 || l0[1] >= G::TY ||
+                (DIM == 3 && (l0[2] < 0 || l0[2] >= G::TZ))) {
+                flags |= ERR_INTERNAL;
+                continue;
+            }
             S1Factors<DIM, SHAPE, R> f;
             s1_factors<DIM, SHAPE, PREC>(&V, s1_load_global<DIM, R>(P, par, k), st, f);
 #pragma unroll 1
@@ -308,21 +328,19 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                     const R wyz = st.w[1][jy] * wz, dyz = st.dw[1][jy] * wz;
                     const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
                     for (int jx = 0; jx < W; ++jx) {
-                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
-                        glb_add(&g[node], lacc_to_acc<PREC>(term_exact<PREC>(f.mx[jx], wyz), flags));
-                        for (int a = 0; a < DIM; ++a)
-                            glb_add(&g[(1 + a) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.px[a][jx], wyz), flags));
-                        glb_add(&g[(1 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.fx[jx], wyz), flags));
-                        glb_add(&g[(2 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.gx[jx], dyz), flags));
-                        if (DIM == 3)
-                            glb_add(&g[(3 + DIM) * NN + node], lacc_to_acc<PREC>(term_exact<PREC>(f.gx[jx], ydz), flags));
+                        const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
+                        lds_add(&tile[li], term_exact<PREC>(f.mx[jx], wyz));
+                        for (int a = 0; a < DIM; ++a) lds_add(&tile[(1 + a) * G::TN + li], term_exact<PREC>(f.px[a][jx], wyz));
+                        lds_add(&tile[(1 + DIM) * G::TN + li], term_exact<PREC>(f.fx[jx], wyz));
+                        lds_add(&tile[(2 + DIM) * G::TN + li], term_exact<PREC>(f.gx[jx], dyz));
+                        if (DIM == 3) lds_add(&tile[(3 + DIM) * G::TN + li], term_exact<PREC>(f.gx[jx], ydz));
                     }
                 }
         }
     }
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, NQ>(P, c0, tile, (A *)P->gA[par], flags);
-    if (flags & ERR_OVERFLOW) atomicOr((uint32_t *)&P->err, ERR_OVERFLOW);
+    flush_tile<DIM, SHAPE, PREC, NQ>(P, t, c0, tile, (A *)P->gA[par], P->haloA, flags);
+    if (flags & (ERR_OVERFLOW | ERR_INTERNAL)) atomicOr((uint32_t *)&P->err, flags & (ERR_OVERFLOW | ERR_INTERNAL));
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
 }
 
@@ -332,7 +350,7 @@ template <int DIM, bool WITH_B> constexpr int stage_stride() { return (WITH_B ? 
 // Stage the tile footprint of nodes, interleaved per node:
 // lds[li * NF + f]: f < DIM vstar, DIM <= f < 2 DIM dvel, 2 DIM <= f v2 (S3).
 template <int DIM, int SHAPE, int PREC, bool WITH_B>
-__device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
+__device__ __forceinline__ void stage_tile(const ProbDev *P, int t, const int c0[3],
                                            typename PrecT<PREC>::real *lds, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
@@ -524,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 
     for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (L)0;
     for (int i = threadIdx.x; i < ND; i += kBlock) hist[i] = 0;
-    stage_tile<DIM, SHAPE, PREC, false>(P, c0, stage, flags);
+    stage_tile<DIM, SHAPE, PREC, false>(P, t, c0, stage, flags);
     __syncthreads();
 
     const bool valid = c0[0] + lc0[0] < P->n[0] && c0[1] + lc0[1] < P->n[1] &&
@@ -632,9 +650,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     }
     if (mismatch) {
         // Particles whose cell changed between sort and use: G2P from the
-        // global grid, P2G straight to the global grid.
-        GLOBAL_AS A *g = gmem((A *)P->gB[par]);
-        const long long NN = P->nnodes;
+        // global grid, P2G into the LDS tile (their cell must still lie in
+        // this tile).
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
@@ -645,6 +662,12 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R>(&V, x, st);
             if (st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2])) continue;
+            const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+            if (l0[0] < 0 || l0[0] >= G::TX || l0[1] < 0 || l0[1] >= G::TY ||
+                (DIM == 3 && (l0[2] < 0 || l0[2] >= G::TZ))) {
+                flags |= ERR_INTERNAL;
+                continue;
+            }
             R vbar[3], dv[3], Gd[9];
             g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
             for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
@@ -658,17 +681,16 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 for (int jy = 0; jy < W; ++jy)
                     for (int jx = 0; jx < W; ++jx) {
                         const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
-                        const long long node = node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0);
+                        const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
                         for (int a = 0; a < DIM; ++a)
-                            glb_add(&g[a * NN + node],
-                                    lacc_to_acc<PREC>(term_exact<PREC>((Ms * v[a]) * st.w[0][jx], wyz), flags));
+                            lds_add(&tile[a * G::TN + li], term_exact<PREC>((Ms * v[a]) * st.w[0][jx], wyz));
                     }
         }
     }
     __shared__ uint32_t ttl[27];
     if (threadIdx.x < 27) ttl[threadIdx.x] = 0;
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, DIM>(P, c0, tile, (A *)P->gB[par], flags);
+    flush_tile<DIM, SHAPE, PREC, DIM>(P, t, c0, tile, (A *)P->gB[par], P->haloB, flags);
     // One global histogram atomic per destination cell of this tile: the
     // tile's particles of that cell get the ranks base .. base + hist - 1.
     // Tile totals are gathered per destination tile (the tile and its
@@ -850,8 +872,32 @@ __global__ __launch_bounds__(1024) void k_tilescan(WorkTab wt) {
     if (threadIdx.x == 1023) P->tbase[n] = wbase + incl;
 }
 
+// The frame nodes that tile t reduces (it is the first tile holding them on
+// both axes): the sum of the halo records of the tiles holding each node,
+// stored into the grid.
+template <int SHAPE, typename A, int NQ>
+__device__ __forceinline__ void reduce_frame(const ProbDev *P, int t, GLOBAL_AS A *grid, const GLOBAL_AS A *halo) {
+    using F = Frame2<SHAPE>;
+    const int tx = t % P->ntile[0], ty = t / P->ntile[0];
+    for (int sl = threadIdx.x; sl < F::NFR; sl += blockDim.x) {
+        int lx, ly;
+        frame_pos<SHAPE>(sl, lx, ly);
+        const int gx = tx * F::T + lx, gy = ty * F::T + ly;
+        if (gx >= P->nn[0] || gy >= P->nn[1]) continue;
+        if (min(gx / F::T, P->ntile[0] - 1) != tx || min(gy / F::T, P->ntile[1] - 1) != ty) continue;
+        const long long node = node_index(P, gx, gy, 0);
+        A raw[NQ];
+        gather_raw<SHAPE, NQ, A>(P, grid, halo, node, gx, gy, raw);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) grid[q * P->nnodes + node] = raw[q];
+    }
+}
+
 // Per tile: offsets of the next order, tile base + prefix of the tile's
-// cell counts (written into offs[parity ^ 1]).
+// cell counts (written into offs[parity ^ 1]).  2D: also the p2 frame nodes
+// this tile reduces, summed from the halo records of S2 into the grid for
+// the update sweep and the read-back.
+template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     __shared__ uint32_t sh[kBlock];
     const int pi = find_prob(wt, blockIdx.x);
@@ -864,6 +910,24 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     const uint32_t ex = block_exclusive_scan(P->count[c], sh, total);
     out[c] = P->tbase[t] + ex;
     if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = P->tbase[P->ntiles];
+    if constexpr (kHalo<DIM>) {
+        using A = typename PrecT<PREC>::acc;
+        reduce_frame<SHAPE, A, DIM>(P, t, gmem((A *)P->gB[P->parity]), gmem((const A *)P->haloB));
+    }
+}
+
+// 2D, right after S1: the frame nodes of the grid, summed from the halo
+// records of S1 by their reducer tiles (one thread per frame position).
+template <int DIM, int SHAPE, int PREC>
+__global__ __launch_bounds__(kBlock) void k_frame_reduce(WorkTab wt) {
+    if constexpr (kHalo<DIM>) {
+        using A = typename PrecT<PREC>::acc;
+        const int pi = find_prob(wt, blockIdx.x);
+        const ProbDev *P = wt.prob[pi];
+        if (!P->active) return;
+        const int t = blockIdx.x - wt.start[pi];
+        reduce_frame<SHAPE, A, 1 + 2 * DIM>(P, t, gmem((A *)P->gA[P->parity]), gmem((const A *)P->haloA));
+    }
 }
 
 template <typename T>
@@ -1204,7 +1268,7 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
     int c0[3], lc[3];
     tile_cell<DIM>(P, t, c0, lc);
     uint32_t flags = 0;
-    stage_tile<DIM, SHAPE, PREC, true>(P, c0, stage, flags);
+    stage_tile<DIM, SHAPE, PREC, true>(P, t, c0, stage, flags);
     // Per destination footprint cell: its offset in the next order plus
     // this tile's base among the cell's particles (only cells that receive
     // particles from this tile are read).
@@ -1395,10 +1459,14 @@ template <int DIM, int SHAPE, int PREC>
 void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
     const dim3 grid(tiles.start[tiles.n]);
     switch (part) {
-    case 0: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 0:
+        hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles);
+        if (kHalo<DIM>)
+            hipLaunchKernelGGL((k_frame_reduce<DIM, SHAPE, PREC>), grid, dim3(Frame2<SHAPE>::NFR), 0, s, tiles);
+        break;
     case 1: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     case 2: hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single); break;
-    case 3: hipLaunchKernelGGL(k_cellscan, grid, dim3(kBlock), 0, s, tiles); break;
+    case 3: hipLaunchKernelGGL((k_cellscan<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     case 4: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     default: hipLaunchKernelGGL(k_finalize, dim3(single.n), dim3(kWideBlock), 0, s, single); break;
     }
