@@ -45,6 +45,9 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     return {
         # X, V, M, rho, e, diag G in; m, p, dt f out; cell offsets in
         "p2g": N * (3 * d + 3) * r + ncells * 4 + nnodes * nq * a,
+        # 2D frame-node sums of the P2G (halo records in, grid out): an
+        # overhead of the P2G's tiling, not algorithmic (S1 counts the grid)
+        "frame_reduce": 0,
         # X, V, M, id in; rank out; m, p, dt f, flags in; p2 out; offsets in
         # (V' and the new key are recomputed by the update sweep)
         "g2p_p2g": N * ((2 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),

@@ -199,12 +199,17 @@ int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last,
 int mpm_counters(mpm_handle *h, uint64_t counters[4], void *hip_stream);
 
 /* Per-sweep timing: runs n_steps steps eagerly with a HIP event after each
- * of the 6 kernels of a step (P2G; G2P + velocity update + P2G of the
- * updated momentum + sort histogram; tile bases of the new order; cell
- * offsets of the new order; G2PD + particle update + move + scatter; time
- * step) and writes the average milliseconds per kernel.  The steps are real
- * steps of the problem.  Synchronises the stream. */
-int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[6], void *hip_stream);
+ * of the MPM_NUM_SWEEPS sweeps of a step and writes the average milliseconds
+ * per sweep, in this order: [0] P2G; [1] 2D frame-node reduction (the sums
+ * of the frame nodes each tile shares with its neighbours; no kernel in 3D,
+ * where those nodes take atomics); [2] G2P + velocity update + P2G of the
+ * updated momentum + sort histogram; [3] tile bases of the new order;
+ * [4] cell offsets of the new order (2D: with the frame-node reduction of
+ * the momentum P2G); [5] G2PD + particle update + move + scatter; [6] time
+ * step.  The steps are real steps of the problem.  Synchronises the
+ * stream. */
+#define MPM_NUM_SWEEPS 7
+int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[MPM_NUM_SWEEPS], void *hip_stream);
 
 /* Nodes per axis (n+1 for Q1, n+2 for B2; 1 for unused axes). */
 int mpm_grid_shape(const mpm_handle *h, int32_t nodes[3]);

@@ -612,7 +612,7 @@ int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stre
     return st;
 }
 
-int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[6], void *hip_stream) {
+int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[MPM_NUM_SWEEPS], void *hip_stream) {
     if (!h || n_steps <= 0 || !ms_per_sweep) return MPM_E_ARG;
     if (h->reported_err) return MPM_E_STATE;
     hipStream_t s = (hipStream_t)hip_stream;

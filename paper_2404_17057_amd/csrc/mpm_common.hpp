@@ -56,7 +56,8 @@ constexpr int kBlock = 256;          // threads per workgroup in every sweep
 constexpr int kScanItems = 16;       // cells per thread in the scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kMaxBatch = 64;        // problems per batched launch
-constexpr int kSweeps = 6;           // kernels per step: p2g, g2p, tile scan, cell scan, update, finalize
+constexpr int kSweeps = 7;           // sweeps per step: p2g, frame reduce (2D), g2p, tile scan, cell scan,
+                                     // update, finalize
 
 struct ProbDev {
     // ---- static geometry and parameters (written once at init)

@@ -1459,15 +1459,15 @@ template <int DIM, int SHAPE, int PREC>
 void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
     const dim3 grid(tiles.start[tiles.n]);
     switch (part) {
-    case 0:
-        hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles);
+    case 0: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 1:
         if (kHalo<DIM>)
             hipLaunchKernelGGL((k_frame_reduce<DIM, SHAPE, PREC>), grid, dim3(Frame2<SHAPE>::NFR), 0, s, tiles);
         break;
-    case 1: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
-    case 2: hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single); break;
-    case 3: hipLaunchKernelGGL((k_cellscan<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
-    case 4: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 2: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 3: hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single); break;
+    case 4: hipLaunchKernelGGL((k_cellscan<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 5: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     default: hipLaunchKernelGGL(k_finalize, dim3(single.n), dim3(kWideBlock), 0, s, single); break;
     }
 }

@@ -28,7 +28,7 @@ G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS = range(7)
 EXPORTS = ["mpm_footprint", "mpm_init", "mpm_step", "mpm_step_batch", "mpm_read_fields",
            "mpm_read_grid", "mpm_status", "mpm_counters", "mpm_profile_step", "mpm_grid_shape",
            "mpm_destroy", "mpm_strerror"]
-SWEEPS = ["p2g", "g2p_p2g", "tilescan", "cellscan", "update", "finalize"]
+SWEEPS = ["p2g", "frame_reduce", "g2p_p2g", "tilescan", "cellscan", "update", "finalize"]
 
 
 class Desc(C.Structure):
