@@ -381,16 +381,22 @@ __device__ __forceinline__ const R *node_ptr(const R *lds, const int l0[3], int 
     return lds + (((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx)) * NF;
 }
 
+// Weight j of an axis by selects (a rolled loop then indexes no array).
+template <int W, typename R> __device__ __forceinline__ R pick(const R w[3], int j) {
+    return W == 3 ? (j == 0 ? w[0] : (j == 1 ? w[1] : w[2])) : (j == 0 ? w[0] : w[1]);
+}
+
 // G2P of one staged vector field (fields OFF..OFF+DIM-1 of the node) at one
 // particle, summed row by row: out = sum_z,y w_z w_y (sum_x w_x f).  S2 and
 // S3 both call this (vstar and dvel), so the same particle gets the same
-// bits in both sweeps.
-template <int DIM, int SHAPE, typename R, int NF, int OFF>
+// bits in both sweeps.  ROLLED keeps the z loop of 3D rolled (fewer live
+// registers; the same operations in the same order).
+template <int DIM, int SHAPE, typename R, int NF, int OFF, bool ROLLED = false>
 __device__ __forceinline__ void g2p_field(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3], R out[3]) {
     constexpr int W = Geo<DIM, SHAPE>::W;
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = 0;
-#pragma unroll
+#pragma unroll (ROLLED ? 1 : 3)
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll
         for (int jy = 0; jy < W; ++jy) {
@@ -401,7 +407,7 @@ __device__ __forceinline__ void g2p_field(const R *lds, const Stencil<DIM, SHAPE
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * nd[OFF + a];
             }
-            const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+            const R wyz = DIM == 3 ? st.w[1][jy] * pick<W, R>(st.w[2], jz) : st.w[1][jy];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) out[a] += wyz * row[a];
         }
@@ -1109,8 +1115,8 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     R dv[3] = {0, 0, 0};
     if constexpr (!GLOBAL) {
         constexpr int NF = stage_stride<DIM, true>();
-        // G2PD of v2, summed row by row
-#pragma unroll
+        // G2PD of v2, summed row by row (z loop rolled: fewer live registers)
+#pragma unroll 1
         for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
@@ -1124,9 +1130,10 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
                         sx[a] += st.dw[0][jx] * nd[2 * DIM + a];
                     }
                 }
-                const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
-                const R dyz = DIM == 3 ? st.dw[1][jy] * st.w[2][jz] : st.dw[1][jy];
-                const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
+                const R wz = DIM == 3 ? pick<W, R>(st.w[2], jz) : (R)1;
+                const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
+                const R dyz = DIM == 3 ? st.dw[1][jy] * wz : st.dw[1][jy];
+                const R ydz = DIM == 3 ? st.w[1][jy] * pick<W, R>(st.dw[2], jz) : (R)0;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
                     Gm[a * DIM + 0] += wyz * sx[a];
@@ -1136,8 +1143,8 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
             }
 #pragma unroll
         for (int c = 0; c < DIM * DIM; ++c) Gm[c] *= inv_h;
-        g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, l0, vbar);
-        g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, l0, dv);
+        g2p_field<DIM, SHAPE, R, NF, 0, true>(stage, st, l0, vbar);
+        g2p_field<DIM, SHAPE, R, NF, DIM, true>(stage, st, l0, dv);
     } else {
         g2p_global<DIM, SHAPE, PREC, true>(P, st, vbar, dv, Gm, flags);
     }
