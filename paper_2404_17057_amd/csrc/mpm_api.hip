@@ -168,6 +168,9 @@ void make_tables(mpm_handle *const *hs, int n, WorkTab &tiles, WorkTab &single) 
     }
     tiles.start[n] = bt; single.start[n] = n;
     tiles.n = single.n = n;
+    int mt = 0;
+    for (int i = 0; i < n; ++i) mt = std::max(mt, hs[i]->host.ntiles);
+    tiles.max_tiles = single.max_tiles = mt;
 }
 
 void enqueue_steps(mpm_handle *const *hs, int n, int steps, hipStream_t s) {

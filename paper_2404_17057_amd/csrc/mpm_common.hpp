@@ -114,6 +114,12 @@ struct WorkTab {
     ProbDev *prob[kMaxBatch];
     int start[kMaxBatch + 1];
     int n;
+    int max_tiles;            // largest tile count of the problems
 };
+
+// Up to this many tiles per problem, the cell-offset scan computes each
+// tile's base itself (the sum of the earlier tiles' totals) and the tile
+// scan is not launched.
+constexpr int kFuseTiles = 4096;
 
 }  // namespace mpm

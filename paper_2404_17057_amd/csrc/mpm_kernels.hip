@@ -900,9 +900,11 @@ __device__ __forceinline__ void reduce_frame(const ProbDev *P, int t, GLOBAL_AS 
 }
 
 // Per tile: offsets of the next order, tile base + prefix of the tile's
-// cell counts (written into offs[parity ^ 1]).  2D: also the p2 frame nodes
-// this tile reduces, summed from the halo records of S2 into the grid for
-// the update sweep and the read-back.
+// cell counts (written into offs[parity ^ 1]).  The tile base comes from the
+// tile scan, or, when every problem of the launch has at most kFuseTiles
+// tiles, is summed here from the earlier tiles' totals.  2D: also the p2
+// frame nodes this tile reduces, summed from the halo records of S2 into
+// the grid for the update sweep and the read-back.
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     __shared__ uint32_t sh[kBlock];
@@ -912,10 +914,30 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     const int t = blockIdx.x - wt.start[pi];
     uint32_t *out = P->offs[P->parity ^ 1];
     const uint32_t c = (uint32_t)t * kBlock + threadIdx.x;
+    const bool fused = wt.max_tiles <= kFuseTiles;
+    __shared__ uint32_t wsum[kBlock / 64];
+    if (fused) {
+        // this thread's share of the earlier tiles' totals, summed per wave;
+        // the scan's barrier below publishes the wave sums
+        const GLOBAL_AS uint32_t *tt = gmem((const uint32_t *)P->ttot);
+        uint32_t run = 0;
+        for (int i = threadIdx.x; i < t; i += kBlock) run += tt[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = run;
+    }
     uint32_t total;
     const uint32_t ex = block_exclusive_scan(P->count[c], sh, total);
-    out[c] = P->tbase[t] + ex;
-    if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = P->tbase[P->ntiles];
+    uint32_t base;
+    if (fused) {
+        base = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) base += wsum[w];
+    } else {
+        base = P->tbase[t];
+    }
+    out[c] = base + ex;
+    if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = base + total;
     if constexpr (kHalo<DIM>) {
         using A = typename PrecT<PREC>::acc;
         reduce_frame<SHAPE, A, DIM>(P, t, gmem((A *)P->gB[P->parity]), gmem((const A *)P->haloB));
@@ -1472,7 +1494,9 @@ void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStr
             hipLaunchKernelGGL((k_frame_reduce<DIM, SHAPE, PREC>), grid, dim3(Frame2<SHAPE>::NFR), 0, s, tiles);
         break;
     case 2: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
-    case 3: hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single); break;
+    case 3:
+        if (tiles.max_tiles > kFuseTiles) hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single);
+        break;
     case 4: hipLaunchKernelGGL((k_cellscan<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     case 5: hipLaunchKernelGGL((k_update<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
     default: hipLaunchKernelGGL(k_finalize, dim3(single.n), dim3(kWideBlock), 0, s, single); break;
