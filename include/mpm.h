@@ -194,8 +194,7 @@ int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last,
 
 /* Diagnostic counters: [0] particles whose cell changed between sort and
  * use (handled on a slow path), [1] particles clamped back through a wall,
- * [2] particles recycled at the outflow, [3] fixed-point contributions that
- * needed the 64-bit conversion path.  Synchronises. */
+ * [2] particles recycled at the outflow, [3] reserved (0).  Synchronises. */
 int mpm_counters(mpm_handle *h, uint64_t counters[4], void *hip_stream);
 
 /* Per-sweep timing: runs n_steps steps eagerly with a HIP event after each

@@ -37,7 +37,7 @@ enum : uint8_t { NF_WALL_X = 1, NF_WALL_Y = 2, NF_WALL_Z = 4, NF_INFLOW = 8, NF_
 enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_WALL = 8u, ERR_INTERNAL = 16u };
 
 // Diagnostic counters (u64).
-enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2, DG_WIDE = 3 };
+enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2 };   // diag[3] is reserved (0)
 
 
 // Per-tile partial results of the update sweep (doubles, stored q-major):

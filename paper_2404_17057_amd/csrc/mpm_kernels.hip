@@ -5,20 +5,24 @@
 // space).  Particles are kept sorted by the tile-major key of their cell, so
 // the particles of a tile are one contiguous range.
 //
-// Per step (all problems of a batch together), six launches:
-//   k_p2g       S1: P2G mass, momentum, impulse dt*f (Sec. 3 (ii)); also
-//               clears the cell histogram of its tile and the frame nodes of
-//               the other grid buffer for the next step
-//   k_g2p       S2: conditions + update on the tile load, G2P, FLIP velocity
-//               update, new cell key and rank, P2G of M V' (Sec. 3 (iii)-(vi));
-//               per-tile totals of the new order
-//   k_tilescan  one workgroup per problem: tile bases of the new order
-//   k_cellscan  per tile: offsets of the new order (tile base + cell prefix)
-//   k_update    S3: conditions on p2 on the tile load, G2PD, energy /
-//               density update, move, recycling, scatter into the new sorted
-//               order; CFL maxima (atomic max of the float bits, exact and
-//               order-free) and FP64 sums per problem (Sec. 3 (vii)-(xi))
-//   k_finalize  one lane per problem: next dt, t, parity (xii)
+// Per step (all problems of a batch together), seven sweeps:
+//   k_p2g          S1: P2G mass, momentum, impulse dt*f (Sec. 3 (ii)); also
+//                  clears the cell histogram of its tile (and, in 3D, the
+//                  frame nodes of the other grid buffer for the next step)
+//   k_frame_reduce 2D: the frame nodes shared by neighbouring tiles, summed
+//                  from the tiles' halo records into the grid
+//   k_g2p          S2: conditions + update on the tile load, G2P, FLIP
+//                  velocity update, new cell and rank, P2G of M V'
+//                  (Sec. 3 (iii)-(vi)); per-tile totals of the new order
+//   k_tilescan     one workgroup per problem: tile bases of the new order
+//                  (only for problems of more than kFuseTiles tiles)
+//   k_cellscan     per tile: offsets of the new order (tile base + cell
+//                  prefix); 2D: the frame nodes of the P2G of S2
+//   k_update       S3: conditions on p2 on the tile load, G2PD, energy /
+//                  density update, move, recycling, scatter into the new
+//                  sorted order; per-tile CFL maxima and FP64 sums
+//                  (Sec. 3 (vii)-(xi))
+//   k_finalize     one workgroup per problem: next dt, t, parity (xii)
 // Grid accumulators and particle arrays are double-buffered by step parity.
 // (An in-kernel "last workgroup" hand-off would need an agent-scope release
 // per workgroup, which on this GPU writes back the whole L2 of an XCD.)
@@ -27,10 +31,11 @@
 // cell and sums their contributions to the cell's stencil nodes in
 // registers (a particle-level pre-reduction: lanes of one instruction touch
 // distinct nodes), then adds the sums into an LDS tile of the footprint
-// nodes, and the tile is added to the global grid with one atomic per
-// non-zero node value.  In the fixed-point precision every contribution is
-// rounded to an int64 quantum before any addition, so all sums are exact
-// and independent of order.
+// nodes.  The nodes only this tile reaches are stored into the grid; the
+// frame shared with neighbouring tiles goes through per-tile halo records
+// (2D) or global atomics (3D).  In the fixed-point precision every
+// contribution is rounded to an int64 quantum before any addition, so all
+// sums are exact and independent of order.
 #include "mpm_device.hpp"
 
 namespace mpm {
