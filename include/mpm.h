@@ -186,7 +186,9 @@ int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stre
 
 /* Time, next and last time step, completed steps and FP64 sums over the
  * particles: mass, momentum (3), internal energy sum M e, kinetic energy
- * sum M |v|^2 / 2.  Synchronises the stream.  Any pointer may be NULL.
+ * sum M |v|^2 / 2, as of the last completed step (with `conserved`, one
+ * small kernel on the stream reduces them from that step's per-tile sums).
+ * Synchronises the stream.  Any pointer may be NULL.
  * Returns the sticky device error (MPM_E_NONPHYSICAL / MPM_E_OVERFLOW),
  * else MPM_OK. */
 int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last,

@@ -18,6 +18,7 @@ void launch_init(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, hi
 void launch_grid_diag(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, int which,
                       double *out, hipStream_t s);
 void launch_arm(const WorkTab &single, const long long *n, hipStream_t s);
+void launch_conserved(ProbDev *dP, hipStream_t s);
 void launch_part(int dim, int shape, int prec, int part, const WorkTab &tiles, const WorkTab &single,
                  hipStream_t s);
 }  // namespace mpm
@@ -498,6 +499,7 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
 int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last, int64_t *step,
                double conserved[6], void *hip_stream) {
     if (!h) return MPM_E_ARG;
+    if (conserved) launch_conserved(h->dev, (hipStream_t)hip_stream);
     ProbDev cur;
     if (read_dynamic(h, &cur, (hipStream_t)hip_stream)) return MPM_E_HIP;
     if (t) *t = cur.t;

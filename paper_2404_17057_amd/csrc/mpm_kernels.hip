@@ -1014,7 +1014,9 @@ __device__ __forceinline__ StepState read_step_state(const ProbDev *P) {
     return s;
 }
 
-__device__ void finalize_problem(ProbDev *P, StepState s, bool advance, const double part[PT_N]) {
+// The next time step from the CFL maxima part[0..1]; with `sums`, also the
+// conserved sums part[2..7].
+__device__ void finalize_problem(ProbDev *P, StepState s, bool advance, const double part[PT_N], bool sums) {
     const double vmax = sqrt(part[0]);
     const double cmax = sqrt(part[1]);
     if (advance) {
@@ -1033,12 +1035,15 @@ __device__ void finalize_problem(ProbDev *P, StepState s, bool advance, const do
         if (dtn < 0.0) dtn = 0.0;
     }
     P->dt = dtn;
-    for (int c = 0; c < 6; ++c) P->cons[c] = part[2 + c];
+    if (sums)
+        for (int c = 0; c < 6; ++c) P->cons[c] = part[2 + c];
     P->active = (s.steps_left > 0 && s.err == 0 && dtn > 0.0 &&
                  (s.t_end <= 0.0 || s.t < s.t_end)) ? 1 : 0;
 }
 
-// Reduction of the per-tile partials of one problem by one workgroup.
+// Reduction of the per-tile partials q0 .. q1-1 of one problem by one
+// workgroup (the others stay 0).
+template <int Q0 = 0, int Q1 = PT_N>
 __device__ __forceinline__ void reduce_tile_partials(const GLOBAL_AS double *partials, int ntiles, double part[PT_N],
                                                      double *red) {
 #pragma unroll
@@ -1046,7 +1051,7 @@ __device__ __forceinline__ void reduce_tile_partials(const GLOBAL_AS double *par
 #pragma unroll 2
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < PT_N; ++q) {
+        for (int q = Q0; q < Q1; ++q) {
             const double v = partials[(long long)q * ntiles + t];
             part[q] = q < 2 ? fmax(part[q], v) : part[q] + v;
         }
@@ -1063,9 +1068,20 @@ __global__ __launch_bounds__(kWideBlock) void k_finalize(WorkTab wt) {
     const GLOBAL_AS double *partials = gmem((const double *)P->partials);
     const StepState st = read_step_state(P);
     if (!active) return;
+    // only the CFL maxima: the conserved sums are reduced when they are read
     double part[PT_N];
-    reduce_tile_partials(partials, ntiles, part, red);
-    if (threadIdx.x == 0) finalize_problem(P, st, true, part);
+    reduce_tile_partials<0, 2>(partials, ntiles, part, red);
+    if (threadIdx.x == 0) finalize_problem(P, st, true, part, false);
+}
+
+// The FP64 conserved sums of the last step (or of the initial state), from
+// the per-tile partials it left; launched when the sums are read.
+__global__ __launch_bounds__(kWideBlock) void k_conserved(ProbDev *P) {
+    __shared__ double red[PT_N * (kWideBlock / 64)];
+    double part[PT_N];
+    reduce_tile_partials<2, PT_N>(gmem((const double *)P->partials), P->ntiles, part, red);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) P->cons[c] = part[2 + c];
 }
 
 // -------------------------------------------------------------------- S3 --
@@ -1439,7 +1455,7 @@ __global__ __launch_bounds__(kWideBlock) void k_init_finalize(ProbDev *P) {
     double part[PT_N];
     reduce_tile_partials(gmem((const double *)P->partials), P->ntiles, part, red);
     if (threadIdx.x != 0) return;
-    finalize_problem(P, read_step_state(P), false, part);
+    finalize_problem(P, read_step_state(P), false, part, true);
     P->active = 0;
     P->parity = 0;
 }
@@ -1591,6 +1607,10 @@ void launch_grid_diag(int dim, int shape, int prec, ProbDev *dP, const ProbDev &
 #define CALL_DIAG(D, S, Pr) launch_grid_diag_t<D, Pr>(dP, h, which, out, s)
     MPM_DISPATCH(dim, shape, prec, CALL_DIAG);
 #undef CALL_DIAG
+}
+
+void launch_conserved(ProbDev *dP, hipStream_t s) {
+    hipLaunchKernelGGL(k_conserved, dim3(1), dim3(kWideBlock), 0, s, dP);
 }
 
 void launch_arm(const WorkTab &single, const long long *n, hipStream_t s) {
