@@ -94,6 +94,11 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, int t, const int c0
     }
 }
 
+// Weight j of an axis by selects (a rolled loop then indexes no array).
+template <int W, typename R> __device__ __forceinline__ R pick(const R w[3], int j) {
+    return W == 3 ? (j == 0 ? w[0] : (j == 1 ? w[1] : w[2])) : (j == 0 ? w[0] : w[1]);
+}
+
 // -------------------------------------------------------------------- S1 --
 // Per-particle factors of S1: x-axis products of the separable stencil sums
 // for mass, momentum and impulse (all in quanta in the fixed-point mode).
@@ -269,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             if (pass == 0) mismatch += own ? 0u : 1u;
             S1Factors<DIM, SHAPE, R> f;
             s1_factors<DIM, SHAPE, PREC>(&V, in, st, f, own);
-            const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
-            const R dwz = DIM == 3 ? st.dw[2][pass] : (R)0;
+            const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
+            const R dwz = DIM == 3 ? pick<W, R>(st.dw[2], pass) : (R)0;
             const double bias = term_bias(k - beg);
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
@@ -329,9 +334,10 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll 1
                 for (int jy = 0; jy < W; ++jy) {
-                    const R wz = DIM == 3 ? st.w[2][jz] : (R)1;
-                    const R wyz = st.w[1][jy] * wz, dyz = st.dw[1][jy] * wz;
-                    const R ydz = DIM == 3 ? st.w[1][jy] * st.dw[2][jz] : (R)0;
+                    const R wz = DIM == 3 ? pick<W, R>(st.w[2], jz) : (R)1;
+                    const R wy = pick<W, R>(st.w[1], jy), dy = pick<W, R>(st.dw[1], jy);
+                    const R wyz = wy * wz, dyz = dy * wz;
+                    const R ydz = DIM == 3 ? wy * pick<W, R>(st.dw[2], jz) : (R)0;
                     for (int jx = 0; jx < W; ++jx) {
                         const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
                         lds_add(&tile[li], term_exact<PREC>(f.mx[jx], wyz));
@@ -384,11 +390,6 @@ template <int DIM, int SHAPE, typename R, int NF>
 __device__ __forceinline__ const R *node_ptr(const R *lds, const int l0[3], int jx, int jy, int jz) {
     using G = Geo<DIM, SHAPE>;
     return lds + (((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx)) * NF;
-}
-
-// Weight j of an axis by selects (a rolled loop then indexes no array).
-template <int W, typename R> __device__ __forceinline__ R pick(const R w[3], int j) {
-    return W == 3 ? (j == 0 ? w[0] : (j == 1 ? w[1] : w[2])) : (j == 0 ? w[0] : w[1]);
 }
 
 // G2P of one staged vector field (fields OFF..OFF+DIM-1 of the node) at one
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll
                 for (int j = 0; j < W; ++j) px[a][j] = mv * st.w[0][j];
             }
-            const R wz = DIM == 3 ? st.w[2][pass] : (R)1;
+            const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
             const double bias = term_bias(k - beg);
 #pragma unroll
             for (int jy = 0; jy < W; ++jy) {
@@ -691,7 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll 1
                 for (int jy = 0; jy < W; ++jy)
                     for (int jx = 0; jx < W; ++jx) {
-                        const R wyz = DIM == 3 ? st.w[1][jy] * st.w[2][jz] : st.w[1][jy];
+                        const R wy = pick<W, R>(st.w[1], jy);
+                        const R wyz = DIM == 3 ? wy * pick<W, R>(st.w[2], jz) : wy;
                         const int li = ((l0[2] + jz) * G::NY + (l0[1] + jy)) * G::NX + (l0[0] + jx);
                         for (int a = 0; a < DIM; ++a)
                             lds_add(&tile[a * G::TN + li], term_exact<PREC>((Ms * v[a]) * st.w[0][jx], wyz));
