@@ -43,8 +43,8 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     r, a = real_sz, acc_sz
     nq = 1 + 2 * d
     return {
-        # X, V, M, rho, e, diag G in; m, p, dt f out; cell offsets in
-        "p2g": N * (3 * d + 3) * r + ncells * 4 + nnodes * nq * a,
+        # X, V, M, rho, e, tr G in; m, p, dt f out; cell offsets in
+        "p2g": N * (2 * d + 4) * r + ncells * 4 + nnodes * nq * a,
         # 2D frame-node sums of the P2G (halo records in, grid out): an
         # overhead of the P2G's tiling, not algorithmic (S1 counts the grid)
         "frame_reduce": 0,
@@ -55,9 +55,10 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
         "tilescan": (ncells // 256) * 8,
         # cell counts in, offsets out
         "cellscan": ncells * 8,
-        # X, V, M, rho, e, diag G, id, rank in; X, V', M, rho, e, G, id out;
-        # m, p, dt f, p2, flags in
-        "update": N * ((3 * d + 3) * r + 8 + (2 * d + 3 + d * d) * r + 4) + nnodes * ((1 + 3 * d) * a + 1),
+        # X, V, M, rho, e, tr G, id, rank in; X, V', M, rho, e, tr G, id out
+        # (the whole G only in the last step of a run); m, p, dt f, p2,
+        # flags in
+        "update": N * ((2 * d + 4) * r + 8 + (2 * d + 4) * r + 4) + nnodes * ((1 + 3 * d) * a + 1),
         "finalize": 0,
     }
 

@@ -167,10 +167,16 @@ enum {
     MPM_F_E = 4,    /* specific internal energy                      */
     MPM_F_P = 5,    /* pressure (gamma-1) rho e                      */
     MPM_F_Q = 6,    /* artificial pressure of the next step          */
-    MPM_F_G = 7,    /* velocity gradient, dim*dim, row-major         */
+    MPM_F_G = 7,    /* velocity gradient, dim*dim, row-major (see    */
+                    /* below)                                        */
     MPM_F_VOL = 8,  /* M / rho                                       */
     MPM_F_ID = 9
 };
+/* A step keeps only tr G per particle (the artificial viscosity reads
+ * nothing else); the whole G is written by the last step of each run
+ * (mpm_step / mpm_step_batch call, or the step reaching t_end).  MPM_F_G
+ * returns MPM_E_STATE, without copying, if the last run stopped early
+ * without an error (a zero time step: every velocity and sound speed 0). */
 int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
                     void *hip_stream);
 

@@ -47,7 +47,7 @@ struct Layout {
 int fields_used(int dim, int f) {
     if (f >= PF_X && f < PF_X + 3) return f - PF_X < dim;
     if (f >= PF_V && f < PF_V + 3) return f - PF_V < dim;
-    if (f >= PF_G) return f - PF_G < dim * dim;
+    if (f >= PF_G && f < PF_G + 9) return f - PF_G < dim * dim;
     return 1;
 }
 
@@ -562,11 +562,8 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
             break;
         case MPM_F_Q: {
             if (fetch(PF_RHO, a) || fetch(PF_E, b)) return MPM_E_HIP;
-            std::vector<double> D((size_t)np, 0.0);
-            for (int ax = 0; ax < dim; ++ax) {
-                if (fetch(PF_G + ax * dim + ax, c2)) return MPM_E_HIP;
-                for (long long k = 0; k < np; ++k) D[k] += c2[k];
-            }
+            std::vector<double> D;
+            if (fetch(PF_D, D)) return MPM_E_HIP;
             const double g = h->host.gamma, hh = h->host.h;
             for (long long k = 0; k < np; ++k) {
                 double q = 0;
@@ -583,6 +580,8 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
             break;
         }
         case MPM_F_G:
+            // the full gradient is written by the last step of each run
+            if (cur.g_step != cur.step && !err_code(cur.err)) return MPM_E_STATE;
             for (int cc = 0; cc < dim * dim; ++cc) {
                 if (fetch(PF_G + cc, a)) return MPM_E_HIP;
                 memcpy(o + cc * np, a.data(), (size_t)np * 8);

@@ -45,7 +45,10 @@ enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2 };   // diag[3] is reserved 
 enum { PT_N = 8 };
 
 // Particle fields stored per parity (arrays of `real`).
-enum { PF_X = 0, PF_V = 3, PF_M = 6, PF_RHO = 7, PF_E = 8, PF_G = 9, PF_N = 18 };
+// Particle fields.  PF_D holds tr G, the only part of the velocity gradient
+// the step itself reads (artificial viscosity); the full G (PF_G, row-major)
+// is written by the last step of each run.
+enum { PF_X = 0, PF_V = 3, PF_M = 6, PF_RHO = 7, PF_E = 8, PF_G = 9, PF_D = 18, PF_N = 19 };
 
 // Tile sizes (cells) per dimension: one lane per cell, 256 lanes per group.
 template <int DIM> struct Tile;
@@ -103,6 +106,7 @@ struct ProbDev {
     long long step, steps_left;
     int active, parity;
     uint32_t err, pad1;
+    long long g_step;     // step count at which PF_G was last written whole
 
     unsigned long long diag[4];
     double cons[6];

@@ -119,12 +119,9 @@ __device__ __forceinline__ S1In<R> s1_load_global(const ProbDev *P, int par, uin
     in.rho = gmem((const R *)P->part[par][PF_RHO])[k];
     in.e = gmem((const R *)P->part[par][PF_E])[k];
     in.v[0] = in.v[1] = in.v[2] = 0;
-    in.D = 0;
+    in.D = gmem((const R *)P->part[par][PF_D])[k];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        in.v[a] = gmem((const R *)P->part[par][PF_V + a])[k];
-        in.D += gmem((const R *)P->part[par][PF_G + a * DIM + a])[k];
-    }
+    for (int a = 0; a < DIM; ++a) in.v[a] = gmem((const R *)P->part[par][PF_V + a])[k];
     return in;
 }
 
@@ -166,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     using A = typename PrecT<PREC>::acc;
     constexpr int NQ = 1 + 2 * DIM;
     constexpr int W = G::W;
-    // Particle fields read per particle: X[DIM], V[DIM], M, rho, e, diag G[DIM]
-    constexpr int NPF = 3 * DIM + 3;
+    // Particle fields read per particle: X[DIM], V[DIM], M, rho, e, tr G
+    constexpr int NPF = 2 * DIM + 4;
     __shared__ L tile[NQ * G::TN];
 
     const int pi = find_prob(wt, blockIdx.x);
@@ -183,11 +180,11 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         for (int a = 0; a < DIM; ++a) {
             src[a] = gmem((const R *)P->part[par0][PF_X + a]);
             src[DIM + a] = gmem((const R *)P->part[par0][PF_V + a]);
-            src[2 * DIM + 3 + a] = gmem((const R *)P->part[par0][PF_G + a * DIM + a]);
         }
         src[2 * DIM] = gmem((const R *)P->part[par0][PF_M]);
         src[2 * DIM + 1] = gmem((const R *)P->part[par0][PF_RHO]);
         src[2 * DIM + 2] = gmem((const R *)P->part[par0][PF_E]);
+        src[2 * DIM + 3] = gmem((const R *)P->part[par0][PF_D]);
     }
     const View V = make_view(P);
 
@@ -255,13 +252,12 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             R x[3] = {0, 0, 0};
             S1In<R> in;
             in.v[0] = in.v[1] = in.v[2] = 0;
-            in.D = 0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 x[a] = cur[a];
                 in.v[a] = cur[DIM + a];
-                in.D += cur[2 * DIM + 3 + a];
             }
+            in.D = cur[2 * DIM + 3];
             in.M = cur[2 * DIM];
             in.rho = cur[2 * DIM + 1];
             in.e = cur[2 * DIM + 2];
@@ -1022,6 +1018,8 @@ __device__ void finalize_problem(ProbDev *P, StepState s, bool advance, const do
     const double vmax = sqrt(part[0]);
     const double cmax = sqrt(part[1]);
     if (advance) {
+        // the update sweep wrote the whole G if this step ends the run
+        if (s.steps_left <= 1 || (s.t_end > 0.0 && !(s.t + s.dt < s.t_end))) P->g_step = s.step + 1;
         P->dt_last = s.dt;
         s.t = s.t + s.dt;
         P->t = s.t;
@@ -1100,15 +1098,16 @@ template <typename R> struct S3In {
 };
 
 template <int DIM, typename R> struct S3Src {
-    const GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *g[3];
+    const GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d;
     const GLOBAL_AS uint32_t *id, *rank;
 };
 
 // Destination arrays of S3 (the next parity) and the next cell offsets.
 template <int DIM, typename R> struct S3Dst {
-    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *g[9];
+    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d, *g[9];
     GLOBAL_AS uint32_t *id;
     const GLOBAL_AS uint32_t *noff;
+    bool full_g;              // the last step of the run: write the whole G too
 };
 
 template <int DIM, typename R>
@@ -1116,12 +1115,11 @@ __device__ __forceinline__ S3In<R> s3_load(const S3Src<DIM, R> &sp, uint32_t k) 
     S3In<R> in;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { in.x[a] = 0; in.v[a] = 0; }
-    in.Dprev = 0;
+    in.Dprev = sp.d[k];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         in.x[a] = sp.x[a][k];
         in.v[a] = sp.v[a][k];
-        in.Dprev += sp.g[a][k];
     }
     in.M = sp.M[k];
     in.rho = sp.rho[k];
@@ -1248,8 +1246,13 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     dst.M[slot] = M;
     dst.rho[slot] = rhon;
     dst.e[slot] = En;
+    // tr G of the stored gradient (zero for a recycled particle): the sum
+    // the next step would form from the stored diagonal, the same bits
+    dst.d[slot] = mv == 1 ? (R)0 : D;
+    if (dst.full_g) {
 #pragma unroll
-    for (int c = 0; c < DIM * DIM; ++c) dst.g[c][slot] = Gm[c];
+        for (int c = 0; c < DIM * DIM; ++c) dst.g[c][slot] = Gm[c];
+    }
     dst.id[slot] = id;
 
     // CFL maxima (squared) and FP64 sums of the new state
@@ -1291,8 +1294,8 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
             const int aa = a < DIM ? a : 0;
             src.x[a] = gmem((const R *)P->part[par0][PF_X + aa]);
             src.v[a] = gmem((const R *)P->part[par0][PF_V + aa]);
-            src.g[a] = gmem((const R *)P->part[par0][PF_G + aa * DIM + aa]);
         }
+        src.d = gmem((const R *)P->part[par0][PF_D]);
         src.M = gmem((const R *)P->part[par0][PF_M]);
         src.rho = gmem((const R *)P->part[par0][PF_RHO]);
         src.e = gmem((const R *)P->part[par0][PF_E]);
@@ -1313,6 +1316,11 @@ __global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
         dst.M = gmem((R *)P->part[np1][PF_M]);
         dst.rho = gmem((R *)P->part[np1][PF_RHO]);
         dst.e = gmem((R *)P->part[np1][PF_E]);
+        dst.d = gmem((R *)P->part[np1][PF_D]);
+        // the run ends with this step when it is its last counted step or
+        // reaches t_end (the same test the time-step kernel makes)
+        const double t_end = P->t_end;
+        dst.full_g = P->steps_left <= 1 || (t_end > 0.0 && !(P->t + P->dt < t_end));
         dst.id = gmem((uint32_t *)P->pid[np1]);
         dst.noff = gmem((const uint32_t *)P->offs[np1]);
     }
@@ -1415,9 +1423,13 @@ __global__ __launch_bounds__(kBlock) void k_init_permute(ProbDev *P) {
     const uint32_t slot = P->offs[0][P->key[k]] + P->rank[k];
     if (slot >= (uint32_t)P->np) { atomicOr((uint32_t *)&P->err, ERR_INTERNAL); return; }
     for (int f = 0; f < PF_N; ++f) {
-        if (!P->part[1][f]) continue;
+        if (!P->part[1][f] || f == PF_D) continue;
         gmem((R *)P->part[0][f])[slot] = gmem((const R *)P->part[1][f])[k];
     }
+    // tr G, summed as the step sums it
+    R D = 0;
+    for (int a = 0; a < DIM; ++a) D += gmem((const R *)P->part[1][PF_G + a * DIM + a])[k];
+    gmem((R *)P->part[0][PF_D])[slot] = D;
     P->pid[0][slot] = P->pid[1][k];
 }
 

@@ -87,6 +87,8 @@ def test_fp64_full_sod_run_matches_oracle():
     rho = s.field(G.F_RHO)
     assert rel_l1(rho, o.particles(O.F_RHO)) <= 1e-6
     assert rel_l1(s.field(G.F_E), o.particles(O.F_E)) <= 1e-6
+    # the whole velocity gradient is written by the step that reaches t_end
+    assert rel_l1(s.read([G.F_G])[G.F_G], o.particles(O.F_G)) <= 1e-4
 
 
 @pytest.mark.parametrize("prec,tol", [(G.FP32_FIX64, 1e-3), (G.FP32_ACC_F64, 1e-3), (G.FP32_ACC_F32, 1e-3)])
@@ -116,6 +118,21 @@ def test_fix64_bitwise_reproducible_and_order_free():
         assert np.array_equal(runs[0][f], runs[2][f]), f
 
 
+def test_fp64_gradient_after_several_steps_matches_oracle():
+    """The step keeps only tr G per particle and writes the whole G in the
+    last step of a run: after a 3-step run, G matches the oracle's."""
+    _gpu()
+    pb = W.cylinder(nx=256, ny=128, steps=10)
+    o = O.Oracle(pb)
+    s = G.Simulation(pb, G.FP64)
+    o.step(3)
+    s.step(3)
+    got = s.read([G.F_G, G.F_Q, G.F_RHO])
+    assert rel_linf(got[G.F_G], o.particles(O.F_G)) <= 1e-8
+    assert rel_linf(got[G.F_Q], o.particles(O.F_Q)) <= 1e-8
+    assert rel_linf(got[G.F_RHO], o.particles(O.F_RHO)) <= 1e-9
+
+
 def test_graph_replay_equals_eager_steps():
     _gpu()
     pb = W.quadrant(n=64)
@@ -124,7 +141,10 @@ def test_graph_replay_equals_eager_steps():
     a.step(35)                     # two graph replays of 16 steps + 3 eager
     for _ in range(35):
         b.step(1)
-    ra, rb = a.read([G.F_X, G.F_RHO, G.F_V]), b.read([G.F_X, G.F_RHO, G.F_V])
+    # G: written whole only by the last step of each run (here step 35 of
+    # one run against every step of 35 runs); Q: from the stored tr G
+    fs = [G.F_X, G.F_RHO, G.F_V, G.F_G, G.F_Q]
+    ra, rb = a.read(fs), b.read(fs)
     for f in ra:
         assert np.array_equal(ra[f], rb[f]), f
     assert a.status()["step"] == b.status()["step"] == 35
