@@ -48,9 +48,10 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
         # 2D frame-node sums of the P2G (halo records in, grid out): an
         # overhead of the P2G's tiling, not algorithmic (S1 counts the grid)
         "frame_reduce": 0,
-        # X, V, M, id in; rank out; m, p, dt f, flags in; p2 out; offsets in
-        # (V' and the new key are recomputed by the update sweep)
-        "g2p_p2g": N * ((2 * d + 1) * r + 8) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
+        # X, V, M in (the id only for a recycled particle); rank out; m, p,
+        # dt f, flags in; p2 out; offsets in (V' and the new key are
+        # recomputed by the update sweep)
+        "g2p_p2g": N * ((2 * d + 1) * r + 4) + ncells * 4 + nnodes * (nq * a + 1 + d * a),
         # tile totals in, tile bases out
         "tilescan": (ncells // 256) * 8,
         # cell counts in, offsets out

@@ -278,8 +278,19 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
 // drawn from splitmix64(seed ^ step<<32 ^ id ^ (a-1)<<56) (reading of the
 // random inflow cell of Sec. 4.1); any other exit is clamped and counted.
 // Returns 1 when the particle was recycled, 2 when clamped, 0 otherwise.
-template <int DIM, typename R, class PP>
-__device__ __forceinline__ int advect(const PP *P, R x[3], const R vbar[3], R dt, uint32_t id) {
+// `id` gives the particle id (a value, or a load made only for a recycled
+// particle).
+struct IdVal {
+    uint32_t v;
+    __device__ uint32_t operator()() const { return v; }
+};
+struct IdAt {
+    const GLOBAL_AS uint32_t *p;
+    uint32_t k;
+    __device__ uint32_t operator()() const { return p[k]; }
+};
+template <int DIM, typename R, class PP, class ID>
+__device__ __forceinline__ int advect(const PP *P, R x[3], const R vbar[3], R dt, const ID &id) {
 #pragma unroll
     for (int a = 0; a < DIM; ++a) x[a] = x[a] + dt * vbar[a];
     if (P->face[0][1] == F_OUTFLOW && x[0] >= (R)P->hi[0]) {
@@ -287,7 +298,7 @@ __device__ __forceinline__ int advect(const PP *P, R x[3], const R vbar[3], R dt
 #pragma unroll
         for (int a = 1; a < DIM; ++a) {
             const unsigned long long word = P->seed ^ ((unsigned long long)P->step << 32) ^
-                                            (unsigned long long)id ^ ((unsigned long long)(a - 1) << 56);
+                                            (unsigned long long)id() ^ ((unsigned long long)(a - 1) << 56);
             const double u = (double)(splitmix64(word) >> 11) * 0x1.0p-53;
             x[a] = (R)(P->lo[a] + (P->hi[a] - P->lo[a]) * u);
         }

@@ -492,7 +492,7 @@ static_assert(DestFoot<3>::N <= 1024 && DestFoot<2>::N <= 1024, "footprint index
 // else straight from the global histogram (flagged).
 template <int DIM, typename R, class PP>
 __device__ __forceinline__ void s2_key_rank(const PP *P, GLOBAL_AS uint32_t *count, GLOBAL_AS uint32_t *ttot, const R x[3],
-                                            const R vbar[3], R dt, uint32_t id, const int c0[3], uint32_t *hist,
+                                            const R vbar[3], R dt, IdAt id, const int c0[3], uint32_t *hist,
                                             uint32_t &nk, uint32_t &rank, uint32_t &flags) {
     R xn[3] = {x[0], x[1], x[2]};
     advect<DIM, R>(P, xn, vbar, dt, id);
@@ -519,7 +519,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     constexpr int W = G::W;
     constexpr int NF = stage_stride<DIM, false>();
     constexpr int ND = DestFoot<DIM>::N;
-    // Particle fields read per particle: X[DIM], V[DIM], M (and the id)
+    // Particle fields read per particle: X[DIM], V[DIM], M (the id only for a
+    // particle recycled at the outflow)
     constexpr int NPF = 2 * DIM + 1;
     __shared__ R stage[NF * G::TN];
     __shared__ L tile[DIM * G::TN];
@@ -579,17 +580,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
 
         R cur[NPF];
-        uint32_t cur_id = 0;
 #pragma unroll
         for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? src[f][beg] : (R)0;
-        if (end > beg) cur_id = idg[beg];
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R nxt[NPF];
             const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
             for (int f = 0; f < NPF; ++f) nxt[f] = src[f][kn];
-            const uint32_t nxt_id = idg[kn];
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -616,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 R vbar[3];
                 g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
                 uint32_t nk, rk;
-                s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, cur_id, c0, hist, nk, rk, flags);
+                s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
                 rankg[k] = rk;
             }
             const R Ms = own ? cur[2 * DIM] * sp : (R)0;
@@ -639,7 +637,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             }
 #pragma unroll
             for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
-            cur_id = nxt_id;
         }
         if (end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
@@ -680,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
             for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
             uint32_t nk, rk;
-            s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, ids[k], c0, hist, nk, rk, flags);
+            s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{ids, k}, c0, hist, nk, rk, flags);
             gmem(P->rank)[k] = rk;
             const R Ms = Mp[k] * sp;
 #pragma unroll 1
@@ -1207,7 +1204,7 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     R rhon = rho / J;
     R En = (R)en;
 
-    const int mv = advect<DIM, R>(V, x, vbar, dt, id);
+    const int mv = advect<DIM, R>(V, x, vbar, dt, IdVal{id});
     if (mv == 1) {
         ++sums.rec;
 #pragma unroll
