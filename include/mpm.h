@@ -184,8 +184,10 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
  * component-major (dim comps except MPM_G_M and MPM_G_FLAGS):
  * raw P2G mass / momentum / force, momentum after the conditions and the
  * update, force after the conditions, re-mapped momentum after the
- * conditions, and the node flags.  Allocates a temporary device buffer.
- * Synchronises the stream. */
+ * conditions, and the node flags.  2D grids hold each node's finished sum
+ * in the state precision (the value the gather sweeps use); 3D grids hold
+ * the accumulator words (exact in the fixed-point mode).  Allocates a
+ * temporary device buffer.  Synchronises the stream. */
 enum { MPM_G_M = 0, MPM_G_P = 1, MPM_G_F = 2, MPM_G_PUPD = 3, MPM_G_P2 = 4,
        MPM_G_FBC = 5, MPM_G_FLAGS = 6 };
 int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);

@@ -1,6 +1,8 @@
 // Device-side building blocks of the MPM step for gfx950.
 #pragma once
 
+#include <type_traits>
+
 #include "mpm_common.hpp"
 
 namespace mpm {
@@ -218,6 +220,26 @@ __device__ __forceinline__ typename PrecT<PREC>::real from_acc(typename PrecT<PR
     }
 }
 
+// Word type of the grid buffers.  A 2D node's sum is finished by exactly one
+// writer (the owning tile's flush, or the reduction of the frame), which
+// stores it scaled to the state precision, the value every reader uses.
+// 3D frame nodes take global atomics, so 3D grids hold accumulator words.
+template <int DIM, int PREC> struct GridW {
+    using type = typename std::conditional<DIM == 2, typename PrecT<PREC>::real, typename PrecT<PREC>::acc>::type;
+};
+
+// Value of a grid word in the state precision (q: its quantum).
+template <int DIM, int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::real grid_val(typename GridW<DIM, PREC>::type w, double q,
+                                                              uint32_t &flags) {
+    if constexpr (DIM == 2) {
+        (void)q; (void)flags;
+        return w;
+    } else {
+        return from_acc<PREC>(w, q, flags);
+    }
+}
+
 // -------------------------------------------------------------- atomics --
 __device__ __forceinline__ void lds_add(long long *p, long long v) {
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
@@ -350,16 +372,22 @@ __device__ __forceinline__ void cell_of(const PP *P, const R x[3], int c[3]) {
 //   v2    = p2/m       with p2 after the momentum conditions
 // Nodes without mass give 0.
 template <int DIM, int PREC>
-__device__ __forceinline__ void stage_A_raw(const ProbDev *P, long long node, const typename PrecT<PREC>::acc raw[1 + 2 * DIM],
-                                            typename PrecT<PREC>::real vstar[3],
-                                            typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
+__device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
+                                        typename PrecT<PREC>::real vstar[3],
+                                        typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
-    const R m = from_acc<PREC>(raw[0], P->q_m, flags);
+    using GW = typename GridW<DIM, PREC>::type;
+    const GLOBAL_AS GW *g = gmem((const GW *)P->gA[P->parity]);
+    const long long NN = P->nnodes;
+    GW raw[1 + 2 * DIM];
+#pragma unroll
+    for (int q = 0; q < 1 + 2 * DIM; ++q) raw[q] = g[q * NN + node];
+    const R m = grid_val<DIM, PREC>(raw[0], P->q_m, flags);
     R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        p[a] = from_acc<PREC>(raw[1 + a], P->q_p, flags);
-        I[a] = from_acc<PREC>(raw[1 + DIM + a], P->q_p, flags);
+        p[a] = grid_val<DIM, PREC>(raw[1 + a], P->q_p, flags);
+        I[a] = grid_val<DIM, PREC>(raw[1 + DIM + a], P->q_p, flags);
     }
     const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) {
@@ -375,30 +403,17 @@ __device__ __forceinline__ void stage_A_raw(const ProbDev *P, long long node, co
 }
 
 template <int DIM, int PREC>
-__device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
-                                        typename PrecT<PREC>::real vstar[3],
-                                        typename PrecT<PREC>::real dvel[3], uint32_t &flags) {
-    using A = typename PrecT<PREC>::acc;
-    const GLOBAL_AS A *g = gmem((const A *)P->gA[P->parity]);
-    const long long NN = P->nnodes;
-    A raw[1 + 2 * DIM];
-#pragma unroll
-    for (int q = 0; q < 1 + 2 * DIM; ++q) raw[q] = g[q * NN + node];
-    stage_A_raw<DIM, PREC>(P, node, raw, vstar, dvel, flags);
-}
-
-template <int DIM, int PREC>
 __device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
                                         typename PrecT<PREC>::real v2[3], uint32_t &flags) {
     using R = typename PrecT<PREC>::real;
-    using A = typename PrecT<PREC>::acc;
-    const GLOBAL_AS A *gA = gmem((const A *)P->gA[P->parity]);
-    const GLOBAL_AS A *gB = gmem((const A *)P->gB[P->parity]);
+    using GW = typename GridW<DIM, PREC>::type;
+    const GLOBAL_AS GW *gA = gmem((const GW *)P->gA[P->parity]);
+    const GLOBAL_AS GW *gB = gmem((const GW *)P->gB[P->parity]);
     const long long NN = P->nnodes;
-    const R m = from_acc<PREC>(gA[node], P->q_m, flags);
+    const R m = grid_val<DIM, PREC>(gA[node], P->q_m, flags);
     R p[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) p[a] = from_acc<PREC>(gB[a * NN + node], P->q_p, flags);
+    for (int a = 0; a < DIM; ++a) p[a] = grid_val<DIM, PREC>(gB[a * NN + node], P->q_p, flags);
     const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) node_bc<DIM, R>(P, fl, node, m, p, false);
     const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
@@ -467,24 +482,17 @@ template <int SHAPE> __device__ __forceinline__ int frame_contrib(int g, int nti
     return 1;
 }
 
-// Raw accumulators q < NQ of node (gx, gy): the grid value of a node owned
-// by one tile, else the sum of the halo entries of the tiles holding it.
-// All candidate entries are loaded at once (a missing second tile re-reads
-// the first entry, which for a frame node is always a frame position, and
-// is masked out), then summed in a fixed order.  Returns true for a frame
-// node.
+// Accumulators q < NQ of frame node (gx, gy): the sum of the halo entries
+// of the tiles holding it.  All candidate entries are loaded at once (a
+// missing second tile re-reads the first entry, which for a frame node is
+// always a frame position, and is masked out), then summed in a fixed
+// order.
 template <int SHAPE, int NQ, typename A>
-__device__ __forceinline__ bool gather_raw(const ProbDev *P, const GLOBAL_AS A *grid, const GLOBAL_AS A *halo,
-                                           long long node, int gx, int gy, A out[NQ]) {
+__device__ __forceinline__ void gather_frame(const ProbDev *P, const GLOBAL_AS A *halo, int gx, int gy, A out[NQ]) {
     using F = Frame2<SHAPE>;
     int tx[2], lx[2], ty[2], ly[2];
     const int cx = frame_contrib<SHAPE>(gx, P->ntile[0], tx, lx);
     const int cy = frame_contrib<SHAPE>(gy, P->ntile[1], ty, ly);
-    if (cx == 1 && cy == 1 && lx[0] >= F::E && lx[0] < F::T && ly[0] >= F::E && ly[0] < F::T) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) out[q] = grid[q * P->nnodes + node];
-        return false;
-    }
     const long long ntl = P->ntiles;
     long long base[4];
     bool use[4];
@@ -507,7 +515,6 @@ __device__ __forceinline__ bool gather_raw(const ProbDev *P, const GLOBAL_AS A *
         for (int c = 0; c < 4; ++c) sum += use[c] ? v[c][q] : (A)0;
         out[q] = sum;
     }
-    return true;
 }
 
 // Problem owning workgroup b of a batched launch.

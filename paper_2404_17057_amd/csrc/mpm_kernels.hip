@@ -65,15 +65,17 @@ __device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], in
 // cleared the step before).
 template <int DIM> constexpr bool kHalo = DIM == 2;
 
-template <int DIM, int SHAPE, int PREC, int NQ>
+// MASS0: value q = 0 is a mass (quantum q_m; the others are momenta, q_p).
+template <int DIM, int SHAPE, int PREC, int NQ, bool MASS0>
 __device__ __forceinline__ void flush_tile(const ProbDev *P, int t, const int c0[3],
                                            const typename PrecT<PREC>::lacc *tile,
-                                           typename PrecT<PREC>::acc *g, void *halo, uint32_t &flags) {
+                                           void *g, void *halo, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using L = typename PrecT<PREC>::lacc;
     using A = typename PrecT<PREC>::acc;
+    using GW = typename GridW<DIM, PREC>::type;
     const long long NN = P->nnodes;
-    GLOBAL_AS A *gg = gmem(g);
+    GLOBAL_AS GW *gg = gmem((GW *)g);
     for (int i = threadIdx.x; i < NQ * G::TN; i += kBlock) {
         const int q = i / G::TN, li = i - q * G::TN;
         const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
@@ -83,7 +85,11 @@ __device__ __forceinline__ void flush_tile(const ProbDev *P, int t, const int c0
                          (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
         const L val = tile[i];
         if (own) {
-            gg[q * NN + node_index(P, gx, gy, gz)] = lacc_to_acc<PREC>(val, flags);
+            const A a = lacc_to_acc<PREC>(val, flags);
+            if constexpr (DIM == 2)
+                gg[q * NN + node_index(P, gx, gy, gz)] = from_acc<PREC>(a, MASS0 && q == 0 ? P->q_m : P->q_p, flags);
+            else
+                gg[q * NN + node_index(P, gx, gy, gz)] = a;
         } else if constexpr (kHalo<DIM>) {
             GLOBAL_AS A *h = gmem((A *)halo);
             h[((long long)q * P->ntiles + t) * Frame2<SHAPE>::NFR + frame_slot<SHAPE>(ix, iy)] =
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, NQ>(P, t, c0, tile, (A *)P->gA[par], P->haloA, flags);
+    flush_tile<DIM, SHAPE, PREC, NQ, true>(P, t, c0, tile, P->gA[par], P->haloA, flags);
     if (flags & (ERR_OVERFLOW | ERR_INTERNAL)) atomicOr((uint32_t *)&P->err, flags & (ERR_OVERFLOW | ERR_INTERNAL));
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
 }
@@ -696,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     __shared__ uint32_t ttl[27];
     if (threadIdx.x < 27) ttl[threadIdx.x] = 0;
     __syncthreads();
-    flush_tile<DIM, SHAPE, PREC, DIM>(P, t, c0, tile, (A *)P->gB[par], P->haloB, flags);
+    flush_tile<DIM, SHAPE, PREC, DIM, false>(P, t, c0, tile, P->gB[par], P->haloB, flags);
     // One global histogram atomic per destination cell of this tile: the
     // tile's particles of that cell get the ranks base .. base + hist - 1.
     // Tile totals are gathered per destination tile (the tile and its
@@ -880,9 +886,11 @@ __global__ __launch_bounds__(1024) void k_tilescan(WorkTab wt) {
 
 // The frame nodes that tile t reduces (it is the first tile holding them on
 // both axes): the sum of the halo records of the tiles holding each node,
-// stored into the grid.
-template <int SHAPE, typename A, int NQ>
-__device__ __forceinline__ void reduce_frame(const ProbDev *P, int t, GLOBAL_AS A *grid, const GLOBAL_AS A *halo) {
+// stored into the grid in the state precision (MASS0: value 0 is a mass).
+template <int SHAPE, int PREC, int NQ, bool MASS0>
+__device__ __forceinline__ void reduce_frame(ProbDev *P, int t, GLOBAL_AS typename PrecT<PREC>::real *grid,
+                                             const GLOBAL_AS typename PrecT<PREC>::acc *halo) {
+    using A = typename PrecT<PREC>::acc;
     using F = Frame2<SHAPE>;
     const int tx = t % P->ntile[0], ty = t / P->ntile[0];
     for (int sl = threadIdx.x; sl < F::NFR; sl += blockDim.x) {
@@ -893,9 +901,12 @@ __device__ __forceinline__ void reduce_frame(const ProbDev *P, int t, GLOBAL_AS 
         if (min(gx / F::T, P->ntile[0] - 1) != tx || min(gy / F::T, P->ntile[1] - 1) != ty) continue;
         const long long node = node_index(P, gx, gy, 0);
         A raw[NQ];
-        gather_raw<SHAPE, NQ, A>(P, grid, halo, node, gx, gy, raw);
+        gather_frame<SHAPE, NQ, A>(P, halo, gx, gy, raw);
+        uint32_t flags = 0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) grid[q * P->nnodes + node] = raw[q];
+        for (int q = 0; q < NQ; ++q)
+            grid[q * P->nnodes + node] = from_acc<PREC>(raw[q], MASS0 && q == 0 ? P->q_m : P->q_p, flags);
+        if (flags) atomicOr((uint32_t *)&P->err, flags);
     }
 }
 
@@ -939,8 +950,9 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     out[c] = base + ex;
     if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = base + total;
     if constexpr (kHalo<DIM>) {
+        using R = typename PrecT<PREC>::real;
         using A = typename PrecT<PREC>::acc;
-        reduce_frame<SHAPE, A, DIM>(P, t, gmem((A *)P->gB[P->parity]), gmem((const A *)P->haloB));
+        reduce_frame<SHAPE, PREC, DIM, false>(P, t, gmem((R *)P->gB[P->parity]), gmem((const A *)P->haloB));
     }
 }
 
@@ -949,12 +961,13 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_frame_reduce(WorkTab wt) {
     if constexpr (kHalo<DIM>) {
+        using R = typename PrecT<PREC>::real;
         using A = typename PrecT<PREC>::acc;
         const int pi = find_prob(wt, blockIdx.x);
-        const ProbDev *P = wt.prob[pi];
+        ProbDev *P = wt.prob[pi];
         if (!P->active) return;
         const int t = blockIdx.x - wt.start[pi];
-        reduce_frame<SHAPE, A, 1 + 2 * DIM>(P, t, gmem((A *)P->gA[P->parity]), gmem((const A *)P->haloA));
+        reduce_frame<SHAPE, PREC, 1 + 2 * DIM, true>(P, t, gmem((R *)P->gA[P->parity]), gmem((const A *)P->haloA));
     }
 }
 
@@ -1476,13 +1489,15 @@ __global__ __launch_bounds__(kWideBlock) void k_init_finalize(ProbDev *P) {
 template <int DIM, int PREC>
 __global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, double *out) {
     using R = typename PrecT<PREC>::real;
-    using A = typename PrecT<PREC>::acc;
+    using GW = typename GridW<DIM, PREC>::type;
     const long long node = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long NN = P->nnodes;
     if (node >= NN) return;
-    const A *gA = (const A *)P->gA[P->parity ^ 1];
-    const A *gB = (const A *)P->gB[P->parity ^ 1];
-    const double qm = PrecT<PREC>::fixed ? P->q_m : 1.0, qp = PrecT<PREC>::fixed ? P->q_p : 1.0;
+    const GW *gA = (const GW *)P->gA[P->parity ^ 1];
+    const GW *gB = (const GW *)P->gB[P->parity ^ 1];
+    // 2D grids hold scaled values already
+    const bool scaled = PrecT<PREC>::fixed && DIM == 3;
+    const double qm = scaled ? P->q_m : 1.0, qp = scaled ? P->q_p : 1.0;
     const double dtl = P->dt_last > 0 ? P->dt_last : 1.0;
     const uint8_t fl = P->nflag[node];
     const double m = (double)gA[node] * qm;
@@ -1496,12 +1511,12 @@ __global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, dou
     }
     // conditions applied in the state precision, as in the sweeps
     uint32_t flags = 0;
-    R mr = from_acc<PREC>(gA[node], P->q_m, flags);
+    R mr = grid_val<DIM, PREC>(gA[node], P->q_m, flags);
     R p[3] = {0, 0, 0}, I[3] = {0, 0, 0};
     for (int a = 0; a < DIM; ++a) {
-        if (which == 4) p[a] = from_acc<PREC>(gB[a * NN + node], P->q_p, flags);
-        else p[a] = from_acc<PREC>(gA[(1 + a) * NN + node], P->q_p, flags);
-        I[a] = from_acc<PREC>(gA[(1 + DIM + a) * NN + node], P->q_p, flags);
+        if (which == 4) p[a] = grid_val<DIM, PREC>(gB[a * NN + node], P->q_p, flags);
+        else p[a] = grid_val<DIM, PREC>(gA[(1 + a) * NN + node], P->q_p, flags);
+        I[a] = grid_val<DIM, PREC>(gA[(1 + DIM + a) * NN + node], P->q_p, flags);
     }
     if (fl) { node_bc<DIM, R>(P, fl, node, mr, p, false); node_bc<DIM, R>(P, fl, node, mr, I, true); }
     for (int a = 0; a < DIM; ++a) {
