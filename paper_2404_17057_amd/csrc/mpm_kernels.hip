@@ -1281,8 +1281,12 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     sums.MK += 0.5 * (double)M * v2;
 }
 
+// Workgroups per CU S3 is compiled for: 2D fixed point keeps four (at most
+// 128 registers per lane).
+template <int DIM, int PREC> constexpr int kUpdateBlocks = DIM == 2 && PREC == P_F32_FIX ? 4 : 1;
+
 template <int DIM, int SHAPE, int PREC>
-__global__ __launch_bounds__(kBlock) void k_update(WorkTab wt) {
+__global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
     constexpr int NF = stage_stride<DIM, true>();
