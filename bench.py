@@ -106,12 +106,21 @@ def time_gpu(pb, precision, steps, warmup, profile_steps):
     st = sim.status()
     if st["rc"] != 0:
         raise RuntimeError(f"device error {st['rc']} during the timed steps")
-    prof = sim.profile(profile_steps) if profile_steps > 0 else {}
     out = dict(ms_total=ms, ms_per_step=ms / steps, value=pb.n_particles * steps / (ms * 1e-3),
-               sweeps_ms=prof, nodes=sim.nnodes, counters=[int(c) for c in sim.counters()],
-               t=st["t"], step=st["step"])
+               nodes=sim.nnodes, counters=[int(c) for c in sim.counters()], t=st["t"], step=st["step"])
     sim.close()
     del sim
+    # Per-sweep times over the same span of steps as the timed region (a
+    # fresh run: the same warm-up, then profile_steps steps, by default as
+    # many as were timed), one HIP event pair per sweep
+    prof = {}
+    if profile_steps != 0:
+        sim = G.Simulation(pb, precision)
+        sim.step(warmup)
+        prof = sim.profile(steps if profile_steps < 0 else profile_steps)
+        sim.close()
+        del sim
+    out["sweeps_ms"] = prof
     torch.cuda.empty_cache()
     return out
 
@@ -196,7 +205,7 @@ def blast3d(args):
     from paper_2404_17057_amd import workloads as W
     pb = W.blast3d(n=args.blast_n, steps=args.blast_steps)
     log(f"blast3d {args.blast_n}^3: {pb.n_particles} particles")
-    r = time_gpu(pb, G.FP32_FIX64, args.blast_steps, args.blast_warmup, 3)
+    r = time_gpu(pb, G.FP32_FIX64, args.blast_steps, args.blast_warmup, -1)
     nt = [(args.blast_n + 7) // 8, (args.blast_n + 7) // 8, (args.blast_n + 3) // 4]
     b = sweep_bytes(pb, r["nodes"], nt[0] * nt[1] * nt[2] * 256, 4, 8)
     step_bytes = sum(b.values())
@@ -235,7 +244,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=-1,
+                    help="steps of the per-sweep profile (-1: as many as timed, 0: none)")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps timed on the host (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -291,15 +301,28 @@ def main():
     ncells = ntiles * 256
     bytes_fix = sweep_bytes(pb, nnodes, ncells, 4, 8)
     sw = fix["sweeps_ms"]
+    # The tile-scan slot holds no kernel at this size (at most 4096 tiles):
+    # its event pair times the profiling overhead alone, taken off the
+    # dominant sweep's time
+    overhead = sw.get("tilescan", 0.0) if ntiles <= 4096 else 0.0
     dominant = max(sw, key=sw.get) if sw else "update"
-    dom_ms = sw.get(dominant, float("nan"))
+    dom_ms = sw.get(dominant, float("nan")) - overhead
     achieved = bytes_fix[dominant] / (dom_ms * 1e-3) / 1e9
+    # every sweep with algorithmic bytes, for comparison with the dominant one
+    sweeps_roofline = {}
+    for k in ("p2g", "g2p_p2g", "cellscan", "update"):
+        if k in sw and bytes_fix[k] > 0:
+            kms = sw[k] - overhead
+            gbps = bytes_fix[k] / (kms * 1e-3) / 1e9
+            sweeps_roofline[k] = {"kernel_ms": round(kms, 5), "algorithmic_MB": round(bytes_fix[k] / 1e6, 2),
+                                  "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
     src_hash = kernel_source_hash()
     traffic = measured_traffic(dominant, pb.name, src_hash)
     step_bytes = sum(bytes_fix.values())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dominant, "kernel_ms": round(dom_ms, 5),
+                "event_overhead_ms": round(overhead, 5),
                 "algorithmic_bytes_per_launch": int(bytes_fix[dominant]),
                 "step_algorithmic_bytes": int(step_bytes),
                 "step_achieved_GBps": round(step_bytes / (fix["ms_per_step"] * 1e-3) / 1e9, 1)}
@@ -377,6 +400,7 @@ def main():
                                           "ms_per_step": round(fp64["ms_per_step"], 5),
                                           "sweeps_ms": fp64["sweeps_ms"]},
         "sweeps_ms": sw,
+        "sweeps_roofline": sweeps_roofline,
         "accuracy_vs_oracle": accuracy,
         "serving": serving,
         "blast3d": blast3d(args) if args.blast3d else None,

@@ -215,7 +215,10 @@ int mpm_counters(mpm_handle *h, uint64_t counters[4], void *hip_stream);
  * updated momentum + sort histogram; [3] tile bases of the new order;
  * [4] cell offsets of the new order (2D: with the frame-node reduction of
  * the momentum P2G); [5] G2PD + particle update + move + scatter; [6] time
- * step.  The steps are real steps of the problem.  Synchronises the
+ * step.  The steps are real steps of the problem, enqueued in batches of
+ * 32 steps.  Each slot's time includes the event's own cost (the barrier
+ * of an event record); a slot with no kernel (slot [3] when every problem
+ * has at most 4096 tiles) measures that cost alone.  Synchronises the
  * stream. */
 #define MPM_NUM_SWEEPS 7
 int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[MPM_NUM_SWEEPS], void *hip_stream);

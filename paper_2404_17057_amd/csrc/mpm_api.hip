@@ -625,25 +625,35 @@ int mpm_profile_step(mpm_handle *h, int64_t n_steps, double ms_per_sweep[MPM_NUM
     make_tables(one, 1, tiles, single);
     const long long armed = n_steps;
     launch_arm(single, &armed, s);
-    hipEvent_t ev[kSweeps + 1];
-    for (int i = 0; i <= kSweeps; ++i)
-        if (hipEventCreate(&ev[i]) != hipSuccess) return MPM_E_HIP;
+    // Steps are enqueued in batches (events for every sweep of up to kBatch
+    // steps), so the device does not wait for the host between steps.
+    constexpr int kBatch = 32;
+    hipEvent_t ev[kBatch][kSweeps + 1];
+    int made = 0, st = MPM_OK;
+    for (int b = 0; b < kBatch && !st; ++b)
+        for (int i = 0; i <= kSweeps && !st; ++i) {
+            st = hip_ok(hipEventCreate(&ev[b][i]));
+            if (!st) ++made;
+        }
     double acc[kSweeps] = {0};
-    int st = MPM_OK;
-    for (long long k = 0; k < n_steps && !st; ++k) {
-        st = hip_ok(hipEventRecord(ev[0], s));
-        for (int part = 0; part < kSweeps && !st; ++part) {
-            launch_part(h->L.dim, h->L.shape, h->L.prec, part, tiles, single, s);
-            st = hip_ok(hipEventRecord(ev[part + 1], s));
+    for (long long k0 = 0; k0 < n_steps && !st; k0 += kBatch) {
+        const int nb = (int)std::min<long long>(kBatch, n_steps - k0);
+        for (int b = 0; b < nb && !st; ++b) {
+            st = hip_ok(hipEventRecord(ev[b][0], s));
+            for (int part = 0; part < kSweeps && !st; ++part) {
+                launch_part(h->L.dim, h->L.shape, h->L.prec, part, tiles, single, s);
+                st = hip_ok(hipEventRecord(ev[b][part + 1], s));
+            }
         }
-        if (!st) st = hip_ok(hipEventSynchronize(ev[kSweeps]));
-        for (int part = 0; part < kSweeps && !st; ++part) {
-            float ms = 0;
-            st = hip_ok(hipEventElapsedTime(&ms, ev[part], ev[part + 1]));
-            acc[part] += ms;
-        }
+        if (!st) st = hip_ok(hipEventSynchronize(ev[nb - 1][kSweeps]));
+        for (int b = 0; b < nb && !st; ++b)
+            for (int part = 0; part < kSweeps && !st; ++part) {
+                float ms = 0;
+                st = hip_ok(hipEventElapsedTime(&ms, ev[b][part], ev[b][part + 1]));
+                acc[part] += ms;
+            }
     }
-    for (int i = 0; i <= kSweeps; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i / (kSweeps + 1)][i % (kSweeps + 1)]);
     if (st) return st;
     for (int part = 0; part < kSweeps; ++part) ms_per_sweep[part] = acc[part] / (double)n_steps;
     return MPM_OK;
