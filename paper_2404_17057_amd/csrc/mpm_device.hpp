@@ -517,6 +517,20 @@ __device__ __forceinline__ void gather_frame(const ProbDev *P, const GLOBAL_AS A
     }
 }
 
+// Tile of local workgroup j (of n) when groups of G consecutive tiles go to
+// one XCD: workgroups are dealt to the 8 XCDs round-robin (j % 8), so tile
+// t = (k / G) * 8G + (j % 8) * G + k % G with k = j / 8 keeps G neighbouring
+// tiles (and, when 8G divides the tile row, the tiles above and below) on
+// the XCD whose L2 holds their shared cache lines.  A bijection on
+// [0, n): the tail beyond the last full 8G block keeps j.
+template <int G>
+__device__ __forceinline__ int xcd_tile(int j, int n) {
+    constexpr int M = 8 * G;
+    if (G <= 1 || j >= (n / M) * M) return j;
+    const int k = j >> 3, x = j & 7;
+    return (k / G) * M + x * G + (k % G);
+}
+
 // Problem owning workgroup b of a batched launch.
 __device__ __forceinline__ int find_prob(const WorkTab &wt, int b) {
     int lo = 0, hi = wt.n - 1;
