@@ -128,11 +128,19 @@ __device__ __forceinline__ void make_stencil(const PP *P, const R x[3], Stencil<
 }
 
 // ---------------------------------------------------------- constitutive --
+// 1/x for x > 0: in FP32 the hardware reciprocal (within 1 ulp; the state
+// is FP32, so a correctly rounded quotient buys nothing), in FP64 a
+// division.
+template <typename R> __device__ __forceinline__ R recip(R x) {
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+    else return (R)1 / x;
+}
+
 template <typename R> __device__ __forceinline__ R eos_p(R gamma, R rho, R e) {
     return (gamma - (R)1) * rho * e;                 // perfect gas (Sec. 2.1)
 }
 template <typename R> __device__ __forceinline__ R sound(R gamma, R rho, R p) {
-    const R c2 = gamma * p / rho;
+    const R c2 = gamma * p * recip(rho);
     return c2 > (R)0 ? sqrt(c2) : (R)0;
 }
 // Artificial pressure (Sec. 2.1, eq. muart), only for div v < 0.
@@ -394,7 +402,7 @@ __device__ __forceinline__ void stage_A(const ProbDev *P, long long node,
         node_bc<DIM, R>(P, fl, node, m, p, false);
         node_bc<DIM, R>(P, fl, node, m, I, true);
     }
-    const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
+    const R inv_m = m > (R)0 ? recip(m) : (R)0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         vstar[a] = (p[a] + I[a]) * inv_m;
@@ -416,7 +424,7 @@ __device__ __forceinline__ void stage_B(const ProbDev *P, long long node,
     for (int a = 0; a < DIM; ++a) p[a] = grid_val<DIM, PREC>(gB[a * NN + node], P->q_p, flags);
     const uint8_t fl = gmem((const uint8_t *)P->nflag)[node];
     if (fl) node_bc<DIM, R>(P, fl, node, m, p, false);
-    const R inv_m = m > (R)0 ? (R)1 / m : (R)0;
+    const R inv_m = m > (R)0 ? recip(m) : (R)0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) v2[a] = p[a] * inv_m;
 }

@@ -155,7 +155,7 @@ __device__ __forceinline__ void s1_factors(const PP *P, const S1In<typename Prec
     // M, M v and the impulse dt (P+Q) (M/rho) / h (the 1/h turns d/ds into d/dx);
     // all zero when `use` is false (the particle is summed elsewhere)
     const R Ms = use ? M * sm : (R)0;
-    const R Fs = use ? (R)P->dt * (p + q) * (M / rho) * (R)P->inv_h * sp : (R)0;
+    const R Fs = use ? (R)P->dt * (p + q) * (M * recip(rho)) * (R)P->inv_h * sp : (R)0;
     R MVs[3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) MVs[a] = use ? M * v[a] * sp : (R)0;
@@ -1220,9 +1220,18 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     const R q = art_visc(V->av_form, (R)V->c0, (R)V->c1, gam, h, rho, p, Dprev);
     const R J = (R)1 + dt * D;
     if (!(J > (R)0)) flags |= ERR_NONPHYS;
-    // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.
-    const double en = (double)e - V->dt * ((double)p + (double)q) * (double)D / (double)rho;
-    R rhon = rho / J;
+    // Internal energy in FP64 registers: e' = e - dt (P+Q) D / rho.  1/rho:
+    // from an FP32 state, the hardware reciprocal and one Newton step in
+    // FP64 (relative error ~1e-14); from an FP64 state, a division.
+    double irho;
+    if constexpr (sizeof(R) == 4) {
+        const double r0 = (double)recip(rho);
+        irho = r0 * fma(-(double)rho, r0, 2.0);
+    } else {
+        irho = 1.0 / (double)rho;
+    }
+    const double en = (double)e - V->dt * ((double)p + (double)q) * (double)D * irho;
+    R rhon = rho * recip(J);
     R En = (R)en;
 
     const int mv = advect<DIM, R>(V, x, vbar, dt, IdVal{id});
@@ -1283,7 +1292,7 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     }
     sums.vmax2 = fmax(sums.vmax2, fmax(v2, vb2));
     const R pn = eos_p(gam, rhon, En);
-    sums.cmax2 = fmax(sums.cmax2, (double)(gam * pn / rhon));
+    sums.cmax2 = fmax(sums.cmax2, (double)(gam * pn * recip(rhon)));
     sums.M += (double)M;
     sums.ME += (double)M * (double)En;
     sums.MK += 0.5 * (double)M * v2;
