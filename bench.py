@@ -40,7 +40,10 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     no clearing of the next step's buffers, no atomic retries)."""
     d = pb.dim
     N = pb.n_particles
-    r, a = real_sz, acc_sz
+    r = real_sz
+    # grid words: 2D grids hold finished sums in the state precision, 3D
+    # grids the accumulator words their atomics need
+    a = real_sz if d == 2 else acc_sz
     nq = 1 + 2 * d
     return {
         # X, V, M, rho, e, tr G in; m, p, dt f out; cell offsets in
