@@ -91,7 +91,9 @@ typedef struct {
     double inflow_rho, inflow_p, inflow_u[3]; /* state imposed at INFLOW faces and
                                                  given to recycled particles       */
     double recycle_mass;    /* mass of a recycled particle                          */
-    int64_t n_particles;
+    int64_t n_particles;    /* at most 2^30 - 4 (FP32 state) or 2^29 - 2 (FP64):
+                               each particle array stays below 4 GiB, else
+                               MPM_E_UNSUPPORTED                                  */
     uint64_t seed;          /* key of the recycling hash                            */
     double t_end;           /* > 0: the last step is shortened to land on t_end     */
     double rho_ref, u_ref;  /* fixed-point references; 0 = derived from the initial

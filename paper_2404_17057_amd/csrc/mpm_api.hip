@@ -58,7 +58,10 @@ int check_desc(const mpm_desc *d, double *h_out) {
     if (d->precision < MPM_FP64 || d->precision > MPM_FP32_FIX64) return MPM_E_ARG;
     if (d->av_form != MPM_AV_PAPER && d->av_form != MPM_AV_BOOK) return MPM_E_ARG;
     if (!(d->gamma > 1.0) || !(d->cfl > 0.0) || d->n_particles < 0) return MPM_E_ARG;
-    if (d->n_particles > 0xFFFFFFF0LL) return MPM_E_UNSUPPORTED;
+    // particle arrays are addressed with 32-bit byte offsets: each must stay
+    // below 4 GiB
+    const long long real_sz = d->precision == MPM_FP64 ? 8 : 4;
+    if (d->n_particles * real_sz > 0xFFFFFFF0LL) return MPM_E_UNSUPPORTED;
     if (d->shape == MPM_Q1 && d->precision != MPM_FP64 && d->precision != MPM_FP32_FIX64)
         return MPM_E_UNSUPPORTED;
     double h = 0;

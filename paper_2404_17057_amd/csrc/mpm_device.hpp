@@ -539,6 +539,19 @@ __device__ __forceinline__ int xcd_tile(int j, int n) {
     return (k / G) * M + x * G + (k % G);
 }
 
+// Element k of a particle array addressed with a 32-bit byte offset (the
+// particle count is limited so that every array stays below 4 GiB): the
+// access then takes the array base from scalar registers plus one vector
+// offset, instead of a 64-bit address computed per access.
+template <typename T>
+__device__ __forceinline__ T ldk(const GLOBAL_AS T *base, uint32_t k) {
+    return *(const GLOBAL_AS T *)((const GLOBAL_AS char *)base + k * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stk(GLOBAL_AS T *base, uint32_t k, T v) {
+    *(GLOBAL_AS T *)((GLOBAL_AS char *)base + k * (uint32_t)sizeof(T)) = v;
+}
+
 // Problem owning workgroup b of a batched launch.
 __device__ __forceinline__ int find_prob(const WorkTab &wt, int b) {
     int lo = 0, hi = wt.n - 1;

@@ -256,13 +256,13 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 
         R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? src[f][beg] : (R)0;
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R nxt[NPF];
             const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = src[f][kn];
+            for (int f = 0; f < NPF; ++f) nxt[f] = ldk(src[f], kn);
             R x[3] = {0, 0, 0};
             S1In<R> in;
             in.v[0] = in.v[1] = in.v[2] = 0;
@@ -595,13 +595,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 
         R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? src[f][beg] : (R)0;
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R nxt[NPF];
             const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = src[f][kn];
+            for (int f = 0; f < NPF; ++f) nxt[f] = ldk(src[f], kn);
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
                 uint32_t nk, rk;
                 s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
-                rankg[k] = rk;
+                stk(rankg, k, rk);
             }
             const R Ms = own ? cur[2 * DIM] * sp : (R)0;
             R px[3][W];
@@ -1133,17 +1133,17 @@ __device__ __forceinline__ S3In<R> s3_load(const S3Src<DIM, R> &sp, uint32_t k) 
     S3In<R> in;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { in.x[a] = 0; in.v[a] = 0; }
-    in.Dprev = sp.d[k];
+    in.Dprev = ldk(sp.d, k);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        in.x[a] = sp.x[a][k];
-        in.v[a] = sp.v[a][k];
+        in.x[a] = ldk(sp.x[a], k);
+        in.v[a] = ldk(sp.v[a], k);
     }
-    in.M = sp.M[k];
-    in.rho = sp.rho[k];
-    in.e = sp.e[k];
-    in.id = sp.id[k];
-    in.rk = sp.rank[k];
+    in.M = ldk(sp.M, k);
+    in.rho = ldk(sp.rho, k);
+    in.e = ldk(sp.e, k);
+    in.id = ldk(sp.id, k);
+    in.rk = ldk(sp.rank, k);
     return in;
 }
 
@@ -1267,20 +1267,20 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        dst.x[a][slot] = x[a];
-        dst.v[a][slot] = v[a];
+        stk(dst.x[a], slot, x[a]);
+        stk(dst.v[a], slot, v[a]);
     }
-    dst.M[slot] = M;
-    dst.rho[slot] = rhon;
-    dst.e[slot] = En;
+    stk(dst.M, slot, M);
+    stk(dst.rho, slot, rhon);
+    stk(dst.e, slot, En);
     // tr G of the stored gradient (zero for a recycled particle): the sum
     // the next step would form from the stored diagonal, the same bits
-    dst.d[slot] = mv == 1 ? (R)0 : D;
+    stk(dst.d, slot, mv == 1 ? (R)0 : D);
     if (dst.full_g) {
 #pragma unroll
-        for (int c = 0; c < DIM * DIM; ++c) dst.g[c][slot] = Gm[c];
+        for (int c = 0; c < DIM * DIM; ++c) stk(dst.g[c], slot, Gm[c]);
     }
-    dst.id[slot] = id;
+    stk(dst.id, slot, id);
 
     // CFL maxima (squared) and FP64 sums of the new state
     double v2 = 0, vb2 = 0;

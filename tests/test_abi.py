@@ -52,6 +52,21 @@ def test_footprint_and_descriptor_checks_on_host():
     assert G.lib().mpm_strerror(G.E_OVERFLOW).decode().startswith("fixed-point")
 
 
+def test_particle_count_limit_on_host():
+    """Particle arrays are addressed with 32-bit byte offsets: the largest
+    count keeps one array below 4 GiB (2^30 - 4 in FP32, 2^29 - 2 in FP64)."""
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    pb = W.cylinder(nx=64, ny=32)
+    n = ctypes.c_size_t()
+    for prec, size in ((G.FP32_FIX64, 4), (G.FP64, 8)):
+        d = G.make_desc(pb, prec)
+        d.n_particles = 0xFFFFFFF0 // size
+        assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == 0
+        d.n_particles += 1
+        assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == G.E_UNSUPPORTED
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(G, "_lib", None)
