@@ -524,6 +524,8 @@ __device__ __forceinline__ void s2_key_rank(const PP *P, GLOBAL_AS uint32_t *cou
     }
 }
 
+constexpr uint32_t kRankBuf = 2048;   // S2: rank words staged in LDS per tile
+
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
@@ -582,9 +584,19 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const R sp = PrecT<PREC>::fixed ? (R)V.inv_q_p : (R)1;
     uint32_t mismatch = 0;
 
+    // Rank words of the tile's particle range [tb, tb + kRankBuf) are
+    // collected in LDS and stored contiguously at the end (a lane per cell
+    // would store them 64 cells apart); the rest of a denser tile directly.
+    GLOBAL_AS uint32_t *rankg = gmem(P->rank);
+    const uint32_t tb = off[(uint32_t)t * G::CELLS];
+    const uint32_t tn = off[(uint32_t)(t + 1) * G::CELLS] - tb;
+    __shared__ uint32_t rbuf[kRankBuf];
+    auto put_rank = [&](uint32_t k, uint32_t rk) {
+        if (k - tb < kRankBuf) rbuf[k - tb] = rk;
+        else stk(rankg, k, rk);
+    };
     // Each lane walks the particles of its cell, loading the next
     // particle's fields while the current one is processed.
-    GLOBAL_AS uint32_t *rankg = gmem(P->rank);
 #pragma unroll 1
     for (int pass = 0; pass < G::PASSES; ++pass) {
         L acc[G::WP][DIM];
@@ -629,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
                 uint32_t nk, rk;
                 s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
-                stk(rankg, k, rk);
+                put_rank(k, rk);
             }
             const R Ms = own ? cur[2 * DIM] * sp : (R)0;
             R px[3][W];
@@ -692,7 +704,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
             uint32_t nk, rk;
             s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{ids, k}, c0, hist, nk, rk, flags);
-            gmem(P->rank)[k] = rk;
+            put_rank(k, rk);
             const R Ms = Mp[k] * sp;
 #pragma unroll 1
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
@@ -710,6 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     __shared__ uint32_t ttl[27];
     if (threadIdx.x < 27) ttl[threadIdx.x] = 0;
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < min(tn, kRankBuf); i += kBlock) stk(rankg, tb + i, rbuf[i]);
     flush_tile<DIM, SHAPE, PREC, DIM, false>(P, t, c0, tile, P->gB[par], P->haloB, flags);
     // One global histogram atomic per destination cell of this tile: the
     // tile's particles of that cell get the ranks base .. base + hist - 1.
