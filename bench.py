@@ -75,21 +75,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, src_hash):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    valid only while the kernel source is the one the counters were taken
-    from."""
+def measured_counters(kernel, workload, src_hash):
+    """Per-launch rocprofv3 figures of a kernel from the committed counter
+    summary (HBM bytes, VALU wave-instructions), valid only while the kernel
+    source is the one the counters were taken from; else {}."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return {}
     try:
         data = json.load(open(path))
         rec = data.get(workload, {}).get(kernel)
         if rec and rec.get("source_hash") == src_hash:
-            return rec.get("bytes_per_launch")
+            return rec
     except Exception:
-        return None
-    return None
+        return {}
+    return {}
 
 
 def time_gpu(pb, precision, steps, warmup, profile_steps):
@@ -320,12 +320,18 @@ def main():
             sweeps_roofline[k] = {"kernel_ms": round(kms, 5), "algorithmic_MB": round(bytes_fix[k] / 1e6, 2),
                                   "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
     src_hash = kernel_source_hash()
-    traffic = measured_traffic(dominant, pb.name, src_hash)
+    counters = measured_counters(dominant, pb.name, src_hash)
+    traffic = counters.get("bytes_per_launch")
+    # VALU issue: one wave64 VALU instruction takes 4 cycles of a SIMD;
+    # 256 CUs x 4 SIMDs at 2.4 GHz
+    valu = counters.get("sq_insts_valu")
+    valu_frac = round(valu * 4 / (1024 * 2.4e9 * dom_ms * 1e-3), 3) if valu else None
     step_bytes = sum(bytes_fix.values())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dominant, "kernel_ms": round(dom_ms, 5),
                 "event_overhead_ms": round(overhead, 5),
+                "valu_issue_frac": valu_frac,
                 "algorithmic_bytes_per_launch": int(bytes_fix[dominant]),
                 "step_algorithmic_bytes": int(step_bytes),
                 "step_achieved_GBps": round(step_bytes / (fix["ms_per_step"] * 1e-3) / 1e9, 1)}
