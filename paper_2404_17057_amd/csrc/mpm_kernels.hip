@@ -992,34 +992,9 @@ __global__ __launch_bounds__(kBlock) void k_frame_reduce(WorkTab wt) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T block_reduce_sum(T v, T *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    const T r = sh[0];
-    __syncthreads();
-    return r;
-}
-template <typename T>
-__device__ __forceinline__ T block_reduce_max(T v, T *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
-    }
-    const T r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 // -------------------------------------------------------------- finalize --
 // Next time step from the per-tile maxima of the step just done (Sec. 2.2,
-// CFL; Sec. 3 (xi)-(xii)), time and conserved sums.  Thread 0 of one
+// CFL; Sec. 3 (xi)-(xii)) and the time.  Thread 0 of one
 // workgroup per problem holds the reduced partials.
 // Time-stepping state of a problem, read in one batch of loads.
 struct StepState {
