@@ -525,6 +525,10 @@ __device__ __forceinline__ void s2_key_rank(const PP *P, GLOBAL_AS uint32_t *cou
 }
 
 constexpr uint32_t kRankBuf = 2048;   // S2: rank words staged in LDS per tile
+// 3D FP32 S2: V' of the tile's first 2048 particles kept in LDS (24 KiB)
+// by the first z-slab pass for the other two (128^3 blast: S2 -7 %; with an
+// FP64 state the larger tile leaves it slower)
+template <int DIM, typename R> constexpr uint32_t kVCacheN = DIM == 3 && sizeof(R) == 4 ? 2048 : 0;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
@@ -591,6 +595,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const uint32_t tb = off[(uint32_t)t * G::CELLS];
     const uint32_t tn = off[(uint32_t)(t + 1) * G::CELLS] - tb;
     __shared__ uint32_t rbuf[kRankBuf];
+    constexpr uint32_t VC = kVCacheN<DIM, R>;
+    __shared__ R vcache[VC > 0 ? DIM * VC : 1];
     auto put_rank = [&](uint32_t k, uint32_t rk) {
         if (k - tb < kRankBuf) rbuf[k - tb] = rk;
         else stk(rankg, k, rk);
@@ -605,15 +611,19 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
 
+        // V of a particle whose V' the first pass cached is not loaded again
+        auto need = [&](int f, uint32_t kk) {
+            return !(pass > 0 && f >= DIM && f < 2 * DIM && kk - tb < VC);
+        };
         R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? ldk(src[f], beg) : (R)0;
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R nxt[NPF];
             const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = ldk(src[f], kn);
+            for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
             R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
@@ -628,12 +638,20 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             if (pass == 0) mismatch += own ? 0u : 1u;
             // G2P of the velocity increment, row by row: V' = V + dv.  V'
             // is not stored (the update sweep recomputes it from the same
-            // staged values, same bits), so every pass computes it.
-            {
+            // staged values, same bits).  In 3D the first pass keeps it in
+            // LDS for the other two.
+            const uint32_t kl = k - tb;
+            if (pass > 0 && kl < VC) {
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) v[a] = vcache[a * VC + kl];
+            } else {
                 R dv[3];
                 g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, lc, dv);
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
+                if (kl < VC)
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) vcache[a * VC + kl] = v[a];
             }
             if (pass == 0 && own) {
                 // G2P of vstar: the move, the new cell key and the rank
