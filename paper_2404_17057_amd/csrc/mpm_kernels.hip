@@ -139,6 +139,41 @@ __device__ __forceinline__ S1In<R> s1_load_global(const ProbDev *P, int par, uin
     return in;
 }
 
+// The per-particle scalars of S1, s[0..4] = M, dt (P+Q) (M/rho) / h and
+// M v[0..2] in quanta (the 1/h turns d/ds into d/dx); all zero when `use`
+// is false (the particle is summed elsewhere).
+template <int DIM, int PREC, class PP>
+__device__ __forceinline__ void s1_scalars(const PP *P, const S1In<typename PrecT<PREC>::real> &in,
+                                           typename PrecT<PREC>::real s[5], bool use) {
+    using R = typename PrecT<PREC>::real;
+    const R gam = (R)P->gamma, h = (R)P->h;
+    const R M = in.M, rho = in.rho, e = in.e, D = in.D;
+    const R p = eos_p(gam, rho, e);
+    const R q = art_visc(P->av_form, (R)P->c0, (R)P->c1, gam, h, rho, p, D);
+    const R sm = PrecT<PREC>::fixed ? (R)P->inv_q_m : (R)1;
+    const R sp = PrecT<PREC>::fixed ? (R)P->inv_q_p : (R)1;
+    s[0] = use ? M * sm : (R)0;
+    s[1] = use ? (R)P->dt * (p + q) * (M * recip(rho)) * (R)P->inv_h * sp : (R)0;
+    s[2] = s[3] = s[4] = (R)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) s[2 + a] = use ? M * in.v[a] * sp : (R)0;
+}
+
+// x-axis products of the S1 scalars.
+template <int DIM, int SHAPE, typename R>
+__device__ __forceinline__ void s1_products(const R s[5], const Stencil<DIM, SHAPE, R> &st,
+                                            S1Factors<DIM, SHAPE, R> &f) {
+    constexpr int W = Geo<DIM, SHAPE>::W;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        f.mx[j] = s[0] * st.w[0][j];
+        f.fx[j] = s[1] * st.dw[0][j];
+        f.gx[j] = s[1] * st.w[0][j];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) f.px[a][j] = s[2 + a] * st.w[0][j];
+    }
+}
+
 template <int DIM, int SHAPE, int PREC, class PP>
 __device__ __forceinline__ void s1_factors(const PP *P, const S1In<typename PrecT<PREC>::real> &in,
                                            const Stencil<DIM, SHAPE, typename PrecT<PREC>::real> &st,
@@ -168,6 +203,9 @@ __device__ __forceinline__ void s1_factors(const PP *P, const S1In<typename Prec
         for (int a = 0; a < DIM; ++a) f.px[a][j] = MVs[a] * st.w[0][j];
     }
 }
+
+// 3D FP32 S1: particles per tile whose scalars are kept in LDS (40 KiB)
+template <int DIM, typename R> constexpr uint32_t kS1CacheN = DIM == 3 && sizeof(R) == 4 ? 2048 : 0;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
@@ -243,6 +281,11 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
 
+    // 3D FP32: the per-particle scalars of the tile's first FC particles,
+    // computed by the first z-slab pass and read by the other two
+    constexpr uint32_t FC = kS1CacheN<DIM, R>;
+    __shared__ R fcache[FC > 0 ? 5 * FC : 1];
+    const uint32_t tb = off[(uint32_t)t * G::CELLS];
     // Each lane walks the particles of its cell; the fields of the next
     // particle are loaded while the current one is summed (the index is
     // clamped, so the last iteration reloads its own particle).
@@ -254,15 +297,17 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
 
+        // a particle whose scalars the first pass cached loads only X again
+        auto need = [&](int f, uint32_t kk) { return !(pass > 0 && f >= DIM && kk - tb < FC); };
         R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg ? ldk(src[f], beg) : (R)0;
+        for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
         for (uint32_t k = beg; k < end; ++k) {
             R nxt[NPF];
             const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = ldk(src[f], kn);
+            for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
             R x[3] = {0, 0, 0};
             S1In<R> in;
             in.v[0] = in.v[1] = in.v[2] = 0;
@@ -282,8 +327,21 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             // deferred loop below (rare).
             const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
             if (pass == 0) mismatch += own ? 0u : 1u;
+            // the particle's scalars: computed, or in 3D cached by the first
+            // pass for the other two
+            R sc[5];
+            const uint32_t kl = k - tb;
+            if (pass > 0 && kl < FC) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) sc[i] = fcache[i * FC + kl];
+            } else {
+                s1_scalars<DIM, PREC>(&V, in, sc, own);
+                if (kl < FC)
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) fcache[i * FC + kl] = sc[i];
+            }
             S1Factors<DIM, SHAPE, R> f;
-            s1_factors<DIM, SHAPE, PREC>(&V, in, st, f, own);
+            s1_products<DIM, SHAPE, R>(sc, st, f);
             const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
             const R dwz = DIM == 3 ? pick<W, R>(st.dw[2], pass) : (R)0;
             const double bias = term_bias(k - beg);
