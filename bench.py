@@ -92,6 +92,28 @@ def measured_counters(kernel, workload, src_hash):
     return {}
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy bandwidth (GB/s, bytes read + written):
+    the HBM rate a plain streaming kernel reaches on this device."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
 def time_gpu(pb, precision, steps, warmup, profile_steps):
     import torch
     from paper_2404_17057_amd import mpm as G
@@ -327,10 +349,13 @@ def main():
     valu = counters.get("sq_insts_valu")
     valu_frac = round(valu * 4 / (1024 * 2.4e9 * dom_ms * 1e-3), 3) if valu else None
     step_bytes = sum(bytes_fix.values())
+    copy_gbps = copy_bandwidth()
+    log(f"device copy: {copy_gbps} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dominant, "kernel_ms": round(dom_ms, 5),
                 "event_overhead_ms": round(overhead, 5),
+                "measured_copy_GBps": copy_gbps,
                 "valu_issue_frac": valu_frac,
                 "algorithmic_bytes_per_launch": int(bytes_fix[dominant]),
                 "step_algorithmic_bytes": int(step_bytes),
