@@ -259,6 +259,42 @@ def blast3d(args):
     return out
 
 
+def aerofoil(args):
+    """Transonic flow (Mach 0.73) past a NACA 2412 section on [0,0.4] x
+    [0,0.27] whose mask and normals come from the sampled signed distance
+    (FP32 state with int64 fixed-point P2G): particle-steps/s over
+    `--aerofoil-steps` steps after the bench warm-up, the per-sweep times;
+    optionally the L1 density error against the oracle on the 160-cell
+    downscale after `--aerofoil-oracle-steps` steps."""
+    import numpy as np
+    from paper_2404_17057_amd import mpm as G
+    from paper_2404_17057_amd import workloads as W
+    pb = W.aerofoil(nx=args.aerofoil_nx, steps=args.aerofoil_steps)
+    log(f"aerofoil {pb.n[0]}x{pb.n[1]}: {pb.n_particles} particles, {int(pb.cell_mask.sum())} masked cells")
+    r = time_gpu(pb, G.FP32_FIX64, args.aerofoil_steps, args.warmup, -1)
+    out = {"workload": pb.name, "particles": pb.n_particles, "masked_cells": int(pb.cell_mask.sum()),
+           "steps": args.aerofoil_steps, "warmup": args.warmup,
+           "value": round(r["value"], 1), "unit": "particle-steps/s",
+           "ms_per_step": round(r["ms_per_step"], 5), "sweeps_ms": r["sweeps_ms"],
+           "t_reached": round(r["t"], 6), "counters": r["counters"]}
+    del pb
+    if args.aerofoil_oracle_steps > 0:
+        from oracle import oracle as O
+        small = W.aerofoil(nx=160, steps=args.aerofoil_oracle_steps)
+        o = O.Oracle(small)
+        o.step(args.aerofoil_oracle_steps)
+        s = G.Simulation(small, G.FP32_FIX64)
+        s.step(args.aerofoil_oracle_steps)
+        l1 = lambda a, ref: float(np.abs(a - ref).sum() / np.abs(ref).sum())
+        out["accuracy_160x108"] = {"steps": args.aerofoil_oracle_steps,
+                                   "rel_l1_density": l1(s.field(G.F_RHO), o.particles(O.F_RHO)),
+                                   "rel_l1_pressure": l1(s.field(G.F_P), o.particles(O.F_P))}
+        s.close()
+        o.close()
+    log(f"aerofoil: {out}")
+    return out
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -292,6 +328,12 @@ def main():
     ap.add_argument("--blast-warmup", type=int, default=5)
     ap.add_argument("--blast-oracle-steps", type=int, default=0,
                     help="oracle steps of the 64^3 downscale for the accuracy figure (0 = skip)")
+    ap.add_argument("--aerofoil", action="store_true",
+                    help="also time the transonic aerofoil (sampled-SDF obstacle) and report it beside the line")
+    ap.add_argument("--aerofoil-nx", type=int, default=1024)
+    ap.add_argument("--aerofoil-steps", type=int, default=2000)
+    ap.add_argument("--aerofoil-oracle-steps", type=int, default=0,
+                    help="steps of the 160-cell aerofoil run against the oracle (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of 256 MiB (reference for counter scaling)")
     args = ap.parse_args()
@@ -438,6 +480,7 @@ def main():
         "accuracy_vs_oracle": accuracy,
         "serving": serving,
         "blast3d": blast3d(args) if args.blast3d else None,
+        "aerofoil": aerofoil(args) if args.aerofoil else None,
         "kernel_source_hash": src_hash,
     }
     if args.calibrate_copy:

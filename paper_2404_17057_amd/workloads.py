@@ -17,6 +17,9 @@ Workloads (all 2D unless stated, ideal gas gamma = 1.4):
                    inner sphere at p=1e3; walls everywhere.
 * ``quadrant``  -- 2x2-quadrant Riemann problem on the unit square, random
                    per-quadrant states; walls everywhere.
+* ``aerofoil``  -- transonic flow (Mach 0.73) past a NACA 4-digit section
+                   given as sampled surface points; its mask and normals come
+                   from the sampled signed distance function (Sec. 3.2).
 
 Particles sit on a regular s^d lattice in every fluid cell at offsets
 (j + 1/2)/s of the cell, each coordinate jittered by U(-0.05, 0.05) cells;
@@ -160,6 +163,107 @@ def circle_obstacle(n, lo, h, dim, shape, center, radius):
     return mask, normal
 
 
+def naca4_profile(code="0012", chord=1.0, leading_edge=(0.0, 0.0), alpha_deg=0.0,
+                  n_side=200):
+    """Closed polygon (2, 2*n_side - 1) sampling a NACA 4-digit section: the
+    stand-in for a profile read from a file of surface points (Sec. 4.1,
+    transonic aerofoil).  `code` = "MPTT": maximum camber M % of the chord at
+    P/10 of the chord, thickness TT %.  Points are cosine-spaced along the
+    chord, upper surface from the trailing edge to the leading edge, then
+    the lower surface back; the trailing edge is closed (thickness
+    polynomial with -0.1036 x^4).  The section is scaled by `chord`, rotated
+    by the angle of attack `alpha_deg` (positive raises the nose) about the
+    quarter-chord point and translated so that the unrotated leading edge
+    sits at `leading_edge`."""
+    m = int(code[0]) / 100.0
+    p = int(code[1]) / 10.0
+    t = int(code[2:]) / 100.0
+    beta = np.linspace(0.0, math.pi, n_side)
+    xc = 0.5 * (1.0 - np.cos(beta))                       # 0 .. 1, clustered at both ends
+    yt = 5.0 * t * (0.2969 * np.sqrt(xc) - 0.1260 * xc - 0.3516 * xc ** 2
+                    + 0.2843 * xc ** 3 - 0.1036 * xc ** 4)
+    if m > 0.0:
+        front = xc < p
+        yc = np.where(front, m / p ** 2 * (2 * p * xc - xc ** 2),
+                      m / (1 - p) ** 2 * ((1 - 2 * p) + 2 * p * xc - xc ** 2))
+        dyc = np.where(front, 2 * m / p ** 2 * (p - xc), 2 * m / (1 - p) ** 2 * (p - xc))
+    else:
+        yc = np.zeros_like(xc)
+        dyc = np.zeros_like(xc)
+    th = np.arctan(dyc)
+    xu, yu = xc - yt * np.sin(th), yc + yt * np.cos(th)
+    xl, yl = xc + yt * np.sin(th), yc - yt * np.cos(th)
+    px = np.concatenate([xu[::-1], xl[1:]]) - 0.25
+    py = np.concatenate([yu[::-1], yl[1:]])
+    a = math.radians(alpha_deg)
+    rx = px * math.cos(a) + py * math.sin(a)
+    ry = -px * math.sin(a) + py * math.cos(a)
+    return np.stack([leading_edge[0] + chord * (rx + 0.25), leading_edge[1] + chord * ry])
+
+
+def polygon_sdf(poly, qx, qy, chunk=16384):
+    """Signed Euclidean distance from the points (qx, qy) to the closed
+    polygon `poly` (2, S): the minimum distance to its S edges, negative
+    inside (even-odd rule).  This is `eq:sdf` with the profile taken as the
+    polyline through the sampled surface points."""
+    ax, ay = poly[0], poly[1]
+    bx, by = np.roll(ax, -1), np.roll(ay, -1)
+    ex, ey = bx - ax, by - ay
+    ee = np.where(ex * ex + ey * ey > 0.0, ex * ex + ey * ey, 1.0)
+    qx = np.asarray(qx, dtype=np.float64).ravel()
+    qy = np.asarray(qy, dtype=np.float64).ravel()
+    out = np.empty(qx.size)
+    for s in range(0, qx.size, chunk):
+        x = qx[s:s + chunk, None]
+        y = qy[s:s + chunk, None]
+        u = np.clip(((x - ax) * ex + (y - ay) * ey) / ee, 0.0, 1.0)
+        dx, dy = x - (ax + u * ex), y - (ay + u * ey)
+        dist = np.sqrt((dx * dx + dy * dy).min(axis=1))
+        straddle = (ay > y) != (by > y)
+        xcross = ax + (y - ay) * ex / np.where(ey != 0.0, ey, 1.0)
+        inside = (straddle & (x < xcross)).sum(axis=1) % 2 == 1
+        out[s:s + chunk] = np.where(inside, -dist, dist)
+    return out
+
+
+def sdf_obstacle(n, lo, h, shape, poly, margin=4):
+    """Cell mask and node normals of a 2D obstacle given as a sampled surface
+    (Sec. 3.2, `eq:sdf`): the signed distance is sampled on the node lattice
+    and at the cell centres; a cell is masked when its centre has negative
+    distance, and each node's normal is the gradient of the node-sampled
+    distance (second-order differences on the node coordinates), scaled to
+    unit length (0 where it vanishes).  The distance is sampled on the
+    window of nodes and cells within `margin` cells of the profile's
+    bounding box; cells outside it lie outside the profile, and nodes
+    outside it get a zero normal (only nodes of masked cells use one)."""
+    ax = [lo[a] + node_axis(n[a], shape) * h for a in range(2)]
+    cx = [lo[a] + (np.arange(n[a]) + 0.5) * h for a in range(2)]
+    win_n, win_c = [], []
+    for a in range(2):
+        lo_a = poly[a].min() - margin * h
+        hi_a = poly[a].max() + margin * h
+        win_n.append(np.nonzero((ax[a] >= lo_a) & (ax[a] <= hi_a))[0])
+        win_c.append(np.nonzero((cx[a] >= lo_a) & (cx[a] <= hi_a))[0])
+    nn = [len(ax[0]), len(ax[1])]
+    normal = np.zeros((2, nn[1], nn[0]))
+    mask = np.zeros((n[1], n[0]), dtype=np.uint8)
+    wx, wy = ax[0][win_n[0]], ax[1][win_n[1]]
+    if len(wx) >= 3 and len(wy) >= 3:
+        mx, my = np.meshgrid(wx, wy, indexing="xy")
+        sd = polygon_sdf(poly, mx, my).reshape(mx.shape)
+        gy, gx = np.gradient(sd, wy, wx)
+        g = np.sqrt(gx * gx + gy * gy)
+        safe = np.where(g > 1e-12, g, 1.0)
+        sl = np.ix_(win_n[1], win_n[0])
+        normal[0][sl] = np.where(g > 1e-12, gx / safe, 0.0)
+        normal[1][sl] = np.where(g > 1e-12, gy / safe, 0.0)
+    if len(win_c[0]) and len(win_c[1]):
+        ccx, ccy = np.meshgrid(cx[0][win_c[0]], cx[1][win_c[1]], indexing="xy")
+        inside = polygon_sdf(poly, ccx, ccy).reshape(ccx.shape) < 0.0
+        mask[np.ix_(win_c[1], win_c[0])] = inside.astype(np.uint8)
+    return mask.ravel(), normal.reshape(2, -1)
+
+
 def _pad3(t, fill):
     t = tuple(t)
     return t + (fill,) * (3 - len(t))
@@ -211,6 +315,41 @@ def cylinder(nx=1024, ny=512, per_axis=2, mach=3.0, jitter=0.05, seed=DEFAULT_SE
     v[0] = mach
     return Problem(
         name=f"cylinder_{nx}x{ny}_ppc{ppc}", dim=2, n=n, lo=lo, hi=hi,
+        faces=((INFLOW, OUTFLOW), (WALL, WALL), (WALL, WALL)),
+        x=x, v=v, mass=np.full(N, m0), rho=np.full(N, rho0),
+        eint=np.full(N, p0 / ((gamma - 1.0) * rho0)), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
+        inflow_rho=rho0, inflow_p=p0, inflow_u=(mach, 0.0, 0.0), recycle_mass=m0,
+        seed=seed, t_end=0.0, steps=steps, cell_mask=mask, node_normal=normal)
+
+
+def aerofoil(nx=640, per_axis=2, mach=0.73, code="2412", alpha_deg=-3.5, chord=0.12,
+             leading_edge=(0.1, 0.135), jitter=0.05, seed=DEFAULT_SEED, shape=B2,
+             av_form=AV_PAPER, steps=2000, cfl=0.3, n_side=200) -> Problem:
+    """Transonic flow past an aerofoil on [0,0.4] x [0,0.27] (Sec. 4.1): the
+    obstacle is given by sampled surface points and its mask and normals
+    come from the sampled signed distance (`sdf_obstacle`).  A NACA
+    4-digit section stands in for the OAT15a profile, whose coordinates are
+    not available.  Inflow at x_lo with u = (mach, 0) in gas with rho = 1.4,
+    p = 1 (so c = 1), outflow (recycling) at x_hi; the y faces are slip
+    walls, as outflow is only supported on the x_hi face."""
+    h = 0.4 / nx
+    ny = int(round(0.27 / h))
+    n = (nx, ny, 1)
+    lo = (0.0, 0.0, 0.0)
+    hi = (0.4, ny * h, 0.0)
+    rho0, p0, gamma = 1.4, 1.0, 1.4
+    poly = naca4_profile(code, chord, leading_edge, alpha_deg, n_side)
+    mask, normal = sdf_obstacle(n, lo, h, shape, poly)
+    rng = np.random.default_rng(seed)
+    x, _ = _lattice(n, lo, h, 2, per_axis, jitter, rng, cell_ok=(1 - mask).reshape(ny, nx))
+    N = x.shape[1]
+    ppc = per_axis ** 2
+    m0 = rho0 * h * h / ppc
+    v = np.zeros((2, N))
+    v[0] = mach
+    return Problem(
+        name=f"aerofoil_naca{code}_{nx}x{ny}_ppc{ppc}", dim=2, n=n, lo=lo, hi=hi,
         faces=((INFLOW, OUTFLOW), (WALL, WALL), (WALL, WALL)),
         x=x, v=v, mass=np.full(N, m0), rho=np.full(N, rho0),
         eint=np.full(N, p0 / ((gamma - 1.0) * rho0)), ids=np.arange(N, dtype=np.uint32),
