@@ -8,6 +8,8 @@ Tolerances:
 * fixed-point results are bit-identical run to run, under a permutation of
   the input order, through graph replays, and alone vs batched.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -415,3 +417,50 @@ def test_many_tiles_take_the_tile_scan():
         got = sm.read([G.F_X, G.F_RHO])
         for f in ref:
             assert np.array_equal(got[f], ref[f]), f
+
+
+def test_blast3d_full_size_symmetry():
+    """The 256^3 blast in the launch configuration the benchmark times
+    (134,217,728 particles, FP32 state, fixed-point P2G), on the unjittered
+    lattice, where the problem is symmetric under the mirror x -> 1 - x and
+    under permutations of the axes.  The oracle keeps these symmetries to
+    FP64 rounding (checked on the CPU at 16^3); after 3 steps every
+    particle's density must equal its images' to FP32 rounding, the total
+    momentum must vanish and the mass stay ΣM.  A wrong index anywhere in
+    the tile decomposition, the XCD tile order, the frame atomics or the
+    pass caches of a full-size launch breaks the symmetry."""
+    _gpu()
+    n = 256
+    pb = W.blast3d(n=n, steps=3, jitter=0.0)
+    h = pb.h
+    m = 2 * n
+    lat = np.rint(pb.x / (h / 2) - 0.5).astype(np.int64)       # lattice index per axis
+    assert np.abs(lat * (h / 2) + h / 4 - pb.x).max() < 1e-9 * h   # exactly on the lattice
+    key = lat[0] + m * (lat[1] + m * lat[2])
+    inv = np.empty(key.size, np.int64)
+    inv[key] = np.arange(key.size)
+    assert np.array_equal(pb.ids, np.arange(key.size, dtype=np.uint32))
+    images = {"mirror_x": inv[(m - 1 - lat[0]) + m * (lat[1] + m * lat[2])],
+              "swap_xy": inv[lat[1] + m * (lat[0] + m * lat[2])],
+              "cycle_xyz": inv[lat[2] + m * (lat[0] + m * lat[1])]}
+    del key, inv, lat
+    mass_sum = float(pb.mass.astype(np.float32).astype(np.float64).sum())
+    s = G.Simulation(pb, G.FP32_FIX64)
+    del pb
+    s.step(3)
+    st = s.status()
+    assert st["rc"] == 0 and st["step"] == 3
+    assert s.counters()[1] == 0
+    rho = s.field(G.F_RHO)
+    s.close()
+    errs = {k: float(np.abs(rho[v] - rho).max() / rho.max()) for k, v in images.items()}
+    print("blast3d 256^3 symmetry (max relative density gap):", errs, flush=True)
+    # measured on MI355X: 1.3e-6 (mirror), 6.1e-7 (axis permutations)
+    for k, e in errs.items():
+        assert e <= 2e-5, (k, e)
+    cons = st["conserved"]
+    print("conserved:", list(cons), flush=True)
+    assert cons[0] == pytest.approx(mass_sum, rel=1e-12)
+    # total momentum against the momentum scale sqrt(2 ΣM · kinetic energy)
+    assert cons[5] > 0
+    assert np.abs(cons[1:4]).max() <= 1e-9 * math.sqrt(2 * cons[0] * cons[5])   # measured 1.3e-11
