@@ -315,6 +315,38 @@ def test_cylinder_full_size_first_step(prec):
     assert s.counters()[1] == 0
 
 
+def test_ablation_config_all_precisions_against_oracle():
+    """The precision-ablation workload (the cylinder at 512x256 with 4x4
+    particles per cell, 2,064,192 particles: 16 particles per cell for the
+    per-cell walks of the P2G sweeps): one FP64 step matches the oracle's
+    grids and particles to 1e-9, and after 10 steps every precision mode is
+    within 1e-5 relative L1 of the oracle's density and energy."""
+    _gpu()
+    pb = W.cylinder(nx=512, ny=256, per_axis=4, steps=1000)
+    assert pb.n_particles == 2064192
+    o = O.Oracle(pb)
+    o.step(1)
+    s = G.Simulation(pb, G.FP64)
+    s.step(1)
+    for gw, ow in GRID_PAIRS:
+        e = rel_linf(s.grid(gw), o.grid(ow))
+        assert e <= 1e-9, (gw, e)
+    got = s.read([G.F_X, G.F_V, G.F_RHO, G.F_E])
+    for gf, of in [(G.F_X, O.F_X), (G.F_V, O.F_V), (G.F_RHO, O.F_RHO), (G.F_E, O.F_E)]:
+        assert rel_linf(got[gf], o.particles(of)) <= 1e-9, gf
+    s.close()
+    o.step(9)
+    rho_o, e_o = o.particles(O.F_RHO), o.particles(O.F_E)
+    for prec in (G.FP64, G.FP32_ACC_F64, G.FP32_ACC_F32, G.FP32_FIX64):
+        s = G.Simulation(pb, prec)
+        s.step(10)
+        assert s.status()["rc"] == 0
+        assert rel_l1(s.field(G.F_RHO), rho_o) <= 1e-5, prec
+        assert rel_l1(s.field(G.F_E), e_o) <= 1e-5, prec
+        s.close()
+    o.close()
+
+
 def _q1_cases():
     return {
         "sod_q1_256x8": W.sod(shape=W.Q1),
