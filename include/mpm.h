@@ -80,7 +80,10 @@ enum { MPM_AV_PAPER = 0, MPM_AV_BOOK = 1 };
 
 typedef struct {
     int32_t dim;            /* 2 or 3                                              */
-    int32_t n[3];           /* cells per axis (>= 2; n[2] ignored in 2D)           */
+    int32_t n[3];           /* cells per axis (>= 2; n[2] ignored in 2D); at most
+                               2^31 cells once each axis is padded to whole tiles
+                               (16x16 in 2D, 8x8x4 in 3D) and 2^31 - 1 nodes, else
+                               MPM_E_UNSUPPORTED                                  */
     double lo[3], hi[3];    /* domain box; cells must be square/cubic (equal h)     */
     int32_t shape;          /* MPM_Q1 or MPM_B2                                     */
     int32_t precision;      /* MPM_FP64 ... MPM_FP32_FIX64                          */

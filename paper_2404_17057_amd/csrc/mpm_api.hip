@@ -75,6 +75,19 @@ int check_desc(const mpm_desc *d, double *h_out) {
         if (d->face[a][0] == MPM_FACE_OUTFLOW || (a > 0 && d->face[a][1] == MPM_FACE_OUTFLOW))
             return MPM_E_UNSUPPORTED;   // outflow (recycling) only at the high-x face
     }
+    // cell keys and tile-major cell indices are 32-bit, node indices are
+    // int: at most 2^31 padded cells and 2^31 - 1 nodes
+    {
+        const int T[3] = {d->dim == 2 ? Tile<2>::X : Tile<3>::X, d->dim == 2 ? Tile<2>::Y : Tile<3>::Y,
+                          d->dim == 2 ? Tile<2>::Z : Tile<3>::Z};
+        const int extra = d->shape == MPM_B2 ? 2 : 1;
+        double cells_pad = 1.0, nodes = 1.0;
+        for (int a = 0; a < d->dim; ++a) {
+            cells_pad *= (double)((d->n[a] + (long long)T[a] - 1) / T[a]) * T[a];
+            nodes *= (double)d->n[a] + extra;
+        }
+        if (cells_pad > 2147483648.0 || nodes > 2147483647.0) return MPM_E_UNSUPPORTED;
+    }
     *h_out = h;
     return MPM_OK;
 }

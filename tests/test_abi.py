@@ -67,6 +67,31 @@ def test_particle_count_limit_on_host():
         assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == G.E_UNSUPPORTED
 
 
+def test_grid_size_limit_on_host():
+    """Cell keys are 32-bit and node indices int: a grid of more than 2^31
+    padded cells or nodes is refused before any layout arithmetic, also for
+    cell counts whose products overflow 64 bits."""
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    n = ctypes.c_size_t()
+    pb = W.blast3d(n=8, steps=1)
+    d = G.make_desc(pb, G.FP32_FIX64)
+    assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == 0
+    # 1288^3 cells: 1288 = 161 tiles of 8 in x and y, 322 tiles of 4 in z,
+    # 2.14e9 cells; (1290)^3 nodes = 2.147e9 <= 2^31 - 1
+    for a in range(3):
+        d.n[a] = 1288
+        d.hi[a] = d.lo[a] + 1288 * 0.001
+    assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == 0
+    d.n[0] = 1296
+    d.hi[0] = d.lo[0] + 1296 * 0.001
+    assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == G.E_UNSUPPORTED
+    for a in range(3):
+        d.n[a] = 2 ** 30
+        d.hi[a] = d.lo[a] + 2 ** 30 * 0.001
+    assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == G.E_UNSUPPORTED
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(G, "_lib", None)
