@@ -92,8 +92,11 @@ typedef struct {
     double cfl;             /* dt = cfl * h / (max|v| + max c)                      */
     int32_t face[3][2];     /* per axis: [low face, high face] type                 */
     double inflow_rho, inflow_p, inflow_u[3]; /* state imposed at INFLOW faces and
-                                                 given to recycled particles       */
-    double recycle_mass;    /* mass of a recycled particle                          */
+                                                 given to recycled particles; with
+                                                 an INFLOW or OUTFLOW face rho > 0,
+                                                 p >= 0, all finite, else MPM_E_ARG */
+    double recycle_mass;    /* mass of a recycled particle (> 0 with an OUTFLOW
+                               face, else MPM_E_ARG)                              */
     int64_t n_particles;    /* at most 2^30 - 4 (FP32 state) or 2^29 - 2 (FP64):
                                each particle array stays below 4 GiB, else
                                MPM_E_UNSUPPORTED                                  */

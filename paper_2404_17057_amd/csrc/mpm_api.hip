@@ -75,6 +75,21 @@ int check_desc(const mpm_desc *d, double *h_out) {
         if (d->face[a][0] == MPM_FACE_OUTFLOW || (a > 0 && d->face[a][1] == MPM_FACE_OUTFLOW))
             return MPM_E_UNSUPPORTED;   // outflow (recycling) only at the high-x face
     }
+    // an INFLOW face imposes, and recycling through an OUTFLOW face
+    // regenerates particles with, the inflow state: it must be physical
+    bool inflow = false, outflow = false;
+    for (int a = 0; a < d->dim; ++a)
+        for (int s = 0; s < 2; ++s) {
+            inflow |= d->face[a][s] == MPM_FACE_INFLOW;
+            outflow |= d->face[a][s] == MPM_FACE_OUTFLOW;
+        }
+    if (inflow || outflow) {
+        if (!(d->inflow_rho > 0) || !isfinite(d->inflow_rho) || !(d->inflow_p >= 0) || !isfinite(d->inflow_p))
+            return MPM_E_ARG;
+        for (int a = 0; a < d->dim; ++a)
+            if (!isfinite(d->inflow_u[a])) return MPM_E_ARG;
+    }
+    if (outflow && (!(d->recycle_mass > 0) || !isfinite(d->recycle_mass))) return MPM_E_ARG;
     // cell keys and tile-major cell indices are 32-bit, node indices are
     // int: at most 2^31 padded cells and 2^31 - 1 nodes
     {
@@ -271,6 +286,7 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
             if (!(x >= d->lo[a] && x < d->hi[a])) return MPM_E_ARG;
             v2 += pp->v[a][k] * pp->v[a][k];
         }
+        if (!isfinite(v2)) return MPM_E_ARG;
         if (!(pp->mass[k] > 0) || !(pp->rho[k] > 0) || !isfinite(pp->eint[k])) return MPM_E_ARG;
         rho_max = std::max(rho_max, pp->rho[k]);
         const double pr = (d->gamma - 1.0) * pp->rho[k] * pp->eint[k];

@@ -92,6 +92,29 @@ def test_grid_size_limit_on_host():
     assert G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n)) == G.E_UNSUPPORTED
 
 
+def test_inflow_state_validated_on_host():
+    """An INFLOW or OUTFLOW face needs a physical inflow state, and an OUTFLOW
+    face a positive recycling mass; wall-only problems ignore them."""
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    n = ctypes.c_size_t()
+    pb = W.cylinder(nx=64, ny=32)
+    fp = lambda d: G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n))
+    assert fp(G.make_desc(pb, G.FP32_FIX64)) == 0
+    for field, value in (("inflow_rho", 0.0), ("inflow_rho", float("inf")), ("inflow_p", -1.0),
+                         ("inflow_p", float("nan")), ("recycle_mass", 0.0)):
+        d = G.make_desc(pb, G.FP32_FIX64)
+        setattr(d, field, value)
+        assert fp(d) == G.E_ARG, (field, value)
+    d = G.make_desc(pb, G.FP32_FIX64)
+    d.inflow_u[1] = float("nan")
+    assert fp(d) == G.E_ARG
+    sod = G.make_desc(W.sod(), G.FP64)
+    sod.inflow_rho = 0.0
+    sod.recycle_mass = 0.0
+    assert fp(sod) == 0
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(G, "_lib", None)

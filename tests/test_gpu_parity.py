@@ -269,6 +269,12 @@ def test_empty_problem_and_errors():
     with pytest.raises(G.MPMError) as ei:
         G.Simulation(bad, G.FP64)
     assert ei.value.code == G.E_ARG
+    nanv = W.Problem(**{**pb.__dict__})
+    nanv.v = pb.v.copy()
+    nanv.v[1, 7] = np.nan
+    with pytest.raises(G.MPMError) as ei:
+        G.Simulation(nanv, G.FP32_FIX64)
+    assert ei.value.code == G.E_ARG
     # a time step far beyond the CFL bound on colliding streams: J <= 0
     col = W.uniform_box(dim=2, n=8, jitter=0.0)
     col.v[0] = np.where(col.x[0] < 0.5, 5.0, -5.0)
