@@ -442,7 +442,7 @@ def main():
         o.step(args.cpu_steps)
         t2 = time.perf_counter()
         cpu = {"value": round(N * args.cpu_steps / (t2 - t1), 1), "unit": "particle-steps/s",
-               "cores": 1, "kind": "oracle",
+               "cores": 1, "kind": "oracle", "host_cpus": os.cpu_count(),
                "sample": f"first {args.cpu_steps} steps of the same {pb.name} problem "
                          f"({N} particles), sequential FP64 C, one host thread; setup {t1 - t0:.1f} s excluded"}
         log(f"cpu oracle: {cpu['value']:.3e} particle-steps/s over {t2 - t1:.1f} s")
