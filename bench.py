@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--blast-warmup", type=int, default=5)
     ap.add_argument("--blast-oracle-steps", type=int, default=0,
                     help="oracle steps of the 64^3 downscale for the accuracy figure (0 = skip)")
+    ap.add_argument("--all-precisions", action="store_true",
+                    help="also time the FP32 state with FP64 and with FP32 accumulators on the same workload")
     ap.add_argument("--aerofoil", action="store_true",
                     help="also time the transonic aerofoil (sampled-SDF obstacle) and report it beside the line")
     ap.add_argument("--aerofoil-nx", type=int, default=1024)
@@ -387,6 +389,16 @@ def main():
     if not args.no_fp64:
         fp64 = time_gpu(pb, G.FP64, args.steps, args.warmup, args.profile_steps)
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/step, {fp64['value']:.4e} particle-steps/s")
+
+    # the other two FP32-state modes (FP64 and FP32 accumulators) on the same
+    # workload and span, for the precision ablation
+    modes = None
+    if args.all_precisions:
+        modes = {"fp32_fix64": round(fix["value"], 1), "fp64": None if fp64 is None else round(fp64["value"], 1)}
+        for name, prec in (("fp32_acc_f64", G.FP32_ACC_F64), ("fp32_acc_f32", G.FP32_ACC_F32)):
+            r = time_gpu(pb, prec, args.steps, args.warmup, 0)
+            modes[name] = round(r["value"], 1)
+        log(f"precision modes: {modes}")
 
     hostinc = host_inclusive(pb, G.FP32_FIX64, args.steps)
     log(f"host-inclusive: {hostinc}")
@@ -508,6 +520,7 @@ def main():
         "accuracy_vs_oracle": accuracy,
         "serving": serving,
         "host_inclusive": hostinc,
+        "precision_modes": modes,
         "blast3d": blast3d(args) if args.blast3d else None,
         "aerofoil": aerofoil(args) if args.aerofoil else None,
         "kernel_source_hash": src_hash,
