@@ -266,6 +266,9 @@ def blast3d(args):
            "step_algorithmic_bytes": int(step_bytes),
            "step_achieved_GBps": round(step_bytes / (r["ms_per_step"] * 1e-3) / 1e9, 1),
            "counters": r["counters"]}
+    if args.blast_fp64:
+        r64 = time_gpu(pb, G.FP64, args.blast_steps, args.blast_warmup, 0)
+        out["fp64"] = {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 4)}
     del pb
     if args.blast_oracle_steps > 0:
         from oracle import oracle as O
@@ -351,6 +354,8 @@ def main():
     ap.add_argument("--blast-n", type=int, default=256)
     ap.add_argument("--blast-steps", type=int, default=100)
     ap.add_argument("--blast-warmup", type=int, default=5)
+    ap.add_argument("--blast-fp64", action="store_true",
+                    help="also time the 3D blast with the plain FP64 state")
     ap.add_argument("--blast-oracle-steps", type=int, default=0,
                     help="oracle steps of the 64^3 downscale for the accuracy figure (0 = skip)")
     ap.add_argument("--all-precisions", action="store_true",
