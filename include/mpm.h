@@ -104,6 +104,16 @@ typedef struct {
     double t_end;           /* > 0: the last step is shortened to land on t_end     */
     double rho_ref, u_ref;  /* fixed-point references; 0 = derived from the initial
                                state (max density; 4 max(|v| + c))                  */
+    double t0;              /* restart: time of the given state (>= 0; 0 = fresh) */
+    int64_t step0;          /* restart: steps already taken (>= 0); keys the
+                               recycling hash, so a resumed run recycles as the
+                               uninterrupted one                                  */
+    double dt0;             /* restart: the next time step (mpm_status dt_next);
+                               <= 0 derives it from the given state. With the
+                               particle fields read back after a run (G and id
+                               included), the same rho_ref / u_ref and these
+                               three values, MPM_FP32_FIX64 resumes bit for bit;
+                               invalid values give MPM_E_ARG                      */
 } mpm_desc;
 
 /* Host particle arrays, all of length n_particles, read only during

@@ -90,6 +90,8 @@ int check_desc(const mpm_desc *d, double *h_out) {
             if (!isfinite(d->inflow_u[a])) return MPM_E_ARG;
     }
     if (outflow && (!(d->recycle_mass > 0) || !isfinite(d->recycle_mass))) return MPM_E_ARG;
+    // restart state
+    if (!(d->t0 >= 0) || !isfinite(d->t0) || d->step0 < 0 || !isfinite(d->dt0)) return MPM_E_ARG;
     // cell keys and tile-major cell indices are 32-bit, node indices are
     // int: at most 2^31 padded cells and 2^31 - 1 nodes
     {
@@ -321,6 +323,11 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
     P.recycle_mass = d->recycle_mass;
     P.seed = d->seed;
     P.t_end = d->t_end;
+    // a resumed run continues the clock and the step count (the step keys the
+    // recycling hash); the given G is the whole gradient of that step
+    P.t = d->t0;
+    P.step = d->step0;
+    P.g_step = d->step0;
     // Fixed-point quanta: powers of two so that scaling is exact.  Mass:
     // 2^-32 of the mass of a cell at the reference density; momentum and
     // impulse: that times the power of two above the reference speed.
@@ -454,6 +461,11 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
         launch_init(dim, d->shape, d->precision, H->dev, P, s);
         st = hip_ok(hipGetLastError());
     }
+    // a resumed run takes the next time step it was given instead of the one
+    // derived from the state (the init reduction sees |V| only, not the
+    // moved-with velocity of the step that produced the state)
+    if (!st && d->dt0 > 0)
+        st = hip_ok(hipMemcpyAsync(&H->dev->dt, &d->dt0, sizeof(double), hipMemcpyHostToDevice, s));
     if (!st) st = hip_ok(hipStreamSynchronize(s));
     if (st) { free(H); return st; }
     *out = H;

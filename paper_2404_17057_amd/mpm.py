@@ -44,6 +44,7 @@ class Desc(C.Structure):
         ("seed", C.c_uint64),
         ("t_end", C.c_double),
         ("rho_ref", C.c_double), ("u_ref", C.c_double),
+        ("t0", C.c_double), ("step0", C.c_int64), ("dt0", C.c_double),
     ]
 
 
@@ -115,8 +116,11 @@ def make_desc(pb, precision: int) -> Desc:
     d.n_particles = pb.n_particles
     d.seed = int(pb.seed) & 0xFFFFFFFFFFFFFFFF
     d.t_end = pb.t_end
-    d.rho_ref = 0.0
-    d.u_ref = 0.0
+    d.rho_ref = float(pb.rho_ref)
+    d.u_ref = float(pb.u_ref)
+    d.t0 = float(pb.t0)
+    d.step0 = int(pb.step0)
+    d.dt0 = float(pb.dt0)
     return d
 
 

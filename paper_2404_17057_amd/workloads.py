@@ -74,6 +74,11 @@ class Problem:
     gradv: Optional[np.ndarray] = None   # (dim*dim, N) or None for zero
     cell_mask: Optional[np.ndarray] = None   # uint8 over cells, x fastest
     node_normal: Optional[np.ndarray] = None  # (dim, nodes) float64, x fastest
+    rho_ref: float = 0.0                 # fixed-point references (0: from the state)
+    u_ref: float = 0.0
+    t0: float = 0.0                      # restart: time, steps taken, next time step
+    step0: int = 0                       # (a fresh start: all 0)
+    dt0: float = 0.0
 
     @property
     def n_particles(self) -> int:

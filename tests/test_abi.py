@@ -115,6 +115,22 @@ def test_inflow_state_validated_on_host():
     assert fp(sod) == 0
 
 
+def test_restart_fields_validated_on_host():
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libmpm.so not built")
+    n = ctypes.c_size_t()
+    fp = lambda d: G.lib().mpm_footprint(ctypes.byref(d), ctypes.byref(n))
+    pb = W.cylinder(nx=64, ny=32)
+    d = G.make_desc(pb, G.FP32_FIX64)
+    d.t0, d.step0, d.dt0 = 0.125, 37, 1e-4
+    assert fp(d) == 0
+    for field, value in (("t0", -1.0), ("t0", float("nan")), ("t0", float("inf")), ("step0", -1),
+                         ("dt0", float("inf")), ("dt0", float("nan"))):
+        d = G.make_desc(pb, G.FP32_FIX64)
+        setattr(d, field, value)
+        assert fp(d) == G.E_ARG, (field, value)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(G, "_lib", None)
