@@ -51,3 +51,39 @@ def test_served_results_equal_alone_runs():
         assert np.abs(rho - ref).sum() / np.abs(ref).sum() <= 1e-3, spec
     summ = S.summarize(done)
     assert summ["requests"] == 10
+
+
+def test_failing_request_does_not_disturb_the_others():
+    """A request whose flow turns non-physical (colliding streams at 40 times
+    the CFL bound: J <= 0 in its first steps) ends with MPM_E_NONPHYSICAL,
+    while the requests batched with it keep results bit-identical to their
+    runs alone."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bad = W.uniform_box(dim=2, n=8, jitter=0.0)
+    bad.v[0] = np.where(bad.x[0] < 0.5, 5.0, -5.0)
+    bad.cfl = 40.0
+    fams = ["sod", "quadrant", "cylinder"]
+    specs = []
+    for i in range(6):
+        fam = fams[i % 3]
+        nx = {"sod": 256, "quadrant": 64, "cylinder": 128}[fam]
+        ny = {"sod": 8, "quadrant": 64, "cylinder": 64}[fam]
+        specs.append(W.RequestSpec(req_id=i, arrival=0.001 * i, family=fam, nx=nx, ny=ny,
+                                   steps=40 + 5 * i, seed=100 + i, mach=3.0))
+    cache = W.LatticeCache()
+    build = lambda s: bad if s.req_id == 2 else W.build_request(s, cache)
+    srv = S.Server(S.GPUBackend(G.FP32_FIX64), build, hbm_budget=1 << 30, max_slots=6, steps_per_launch=16)
+    done = {d.req_id: d for d in srv.run(specs)}
+    assert len(done) == len(specs)
+    assert done[2].status == G.E_NONPHYSICAL
+    for i, spec in enumerate(specs):
+        if i == 2:
+            continue
+        assert done[i].status == 0, i
+        sim = G.Simulation(build(spec), G.FP32_FIX64)
+        sim.step(spec.steps)
+        rho = sim.field(G.F_RHO)
+        sim.close()
+        assert hashlib.sha256(rho.tobytes()).hexdigest() == done[i].digest, spec
