@@ -67,6 +67,22 @@ def sweep_bytes(pb, nnodes, ncells, real_sz, acc_sz):
     }
 
 
+def survey_bytes(dim, N, nnodes):
+    """Algorithmic bytes per launch of the three particle sweeps as the hot-
+    path scope defines them: FP32 particle fields, 8-byte grid words, no
+    sort, halo or clearing.  S1 reads X, V, M, rho, e and diag G and writes
+    m, p, dt f; S2 reads X, V, M and those grid words and writes V and p2;
+    S3 reads X, rho, e, diag G (and M in 3D), the grid words it needs, and
+    writes X, rho, e, G (and Vol in 3D)."""
+    d = dim
+    s3_part = (2 * d + 2 + d + 2 + d * d) * 4 if d == 2 else (2 * d + 3 + d + 3 + d * d) * 4
+    return {
+        "p2g": N * (3 * d + 3) * 4 + nnodes * (1 + 2 * d) * 8,
+        "g2p_p2g": N * (3 * d + 1) * 4 + nnodes * (1 + 3 * d) * 8,
+        "update": N * s3_part + nnodes * (1 + 3 * d) * 8,
+    }
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("mpm_kernels.hip", "mpm_device.hpp", "mpm_common.hpp"):
@@ -115,11 +131,18 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
 
 
 def time_gpu(pb, precision, steps, warmup, profile_steps):
+    """Steps/s of one precision mode.  The first mpm_step call of a problem
+    captures its step graphs (host work, before anything is timed); its host
+    time is reported as `graph_setup_ms`.  The warm-up is that first call,
+    so the timed steps are graph replays only."""
     import torch
     from paper_2404_17057_amd import mpm as G
     sim = G.Simulation(pb, precision)
     stream = torch.cuda.current_stream()
-    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(max(warmup, 1))
+    setup_ms = (time.perf_counter() - t0) * 1e3   # asynchronous call: capture + enqueue
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -132,7 +155,8 @@ def time_gpu(pb, precision, steps, warmup, profile_steps):
     if st["rc"] != 0:
         raise RuntimeError(f"device error {st['rc']} during the timed steps")
     out = dict(ms_total=ms, ms_per_step=ms / steps, value=pb.n_particles * steps / (ms * 1e-3),
-               nodes=sim.nnodes, counters=[int(c) for c in sim.counters()], t=st["t"], step=st["step"])
+               nodes=sim.nnodes, counters=[int(c) for c in sim.counters()], t=st["t"], step=st["step"],
+               graph_setup_ms=round(setup_ms, 3), warmup_steps=max(warmup, 1))
     sim.close()
     del sim
     # Per-sweep times over the same span of steps as the timed region (a
@@ -141,7 +165,7 @@ def time_gpu(pb, precision, steps, warmup, profile_steps):
     prof = {}
     if profile_steps != 0:
         sim = G.Simulation(pb, precision)
-        sim.step(warmup)
+        sim.step(max(warmup, 1))
         prof = sim.profile(steps if profile_steps < 0 else profile_steps)
         sim.close()
         del sim
@@ -259,12 +283,26 @@ def blast3d(args):
     nt = [(args.blast_n + 7) // 8, (args.blast_n + 7) // 8, (args.blast_n + 3) // 4]
     b = sweep_bytes(pb, r["nodes"], nt[0] * nt[1] * nt[2] * 256, 4, 8)
     step_bytes = sum(b.values())
+    sb = survey_bytes(3, pb.n_particles, r["nodes"])
+    sw = r["sweeps_ms"]
+    dom = max(("p2g", "g2p_p2g", "update"), key=lambda k: sw.get(k, 0.0)) if sw else "p2g"
+    roof = None
+    if sw:
+        dom_ms = sw[dom]
+        ach = sb[dom] / (dom_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "kernel_ms": round(dom_ms, 4),
+                "algorithmic_bytes_per_launch": int(sb[dom]), "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                "sweeps_frac": {k: round(sb[k] / (sw[k] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                                for k in sb if sw.get(k)}}
     out = {"workload": f"blast3d_{args.blast_n}^3_ppc8", "particles": pb.n_particles,
-           "steps": args.blast_steps, "warmup": args.blast_warmup,
+           "steps": args.blast_steps, "warmup": r["warmup_steps"],
            "value": round(r["value"], 1), "unit": "particle-steps/s",
-           "ms_per_step": round(r["ms_per_step"], 4), "sweeps_ms": r["sweeps_ms"],
+           "ms_per_step": round(r["ms_per_step"], 4), "graph_setup_ms": r["graph_setup_ms"],
+           "sweeps_ms": sw, "roofline": roof,
+           "step_algorithmic_bytes_scope": int(sum(sb.values())),
+           "step_achieved_GBps_scope": round(sum(sb.values()) / (r["ms_per_step"] * 1e-3) / 1e9, 1),
            "step_algorithmic_bytes": int(step_bytes),
-           "step_achieved_GBps": round(step_bytes / (r["ms_per_step"] * 1e-3) / 1e9, 1),
            "counters": r["counters"]}
     if args.blast_fp64:
         r64 = time_gpu(pb, G.FP64, args.blast_steps, args.blast_warmup, 0)
@@ -273,12 +311,12 @@ def blast3d(args):
     if args.blast_oracle_steps > 0:
         from oracle import oracle as O
         small = W.blast3d(n=64, steps=args.blast_oracle_steps)
-        o = O.Oracle(small)
+        o = O.Oracle(small, threads=os.cpu_count() or 1)
         o.step(args.blast_oracle_steps)
         s = G.Simulation(small, G.FP32_FIX64)
         s.step(args.blast_oracle_steps)
         l1 = lambda a, ref: float(np.abs(a - ref).sum() / np.abs(ref).sum())
-        out["accuracy_64^3"] = {"steps": args.blast_oracle_steps,
+        out["accuracy_64^3"] = {"steps": args.blast_oracle_steps, "oracle_threads": o.threads,
                                 "rel_l1_density": l1(s.field(G.F_RHO), o.particles(O.F_RHO)),
                                 "rel_l1_pressure": l1(s.field(G.F_P), o.particles(O.F_P))}
         s.close()
@@ -349,15 +387,16 @@ def main():
                          "(prints its own JSON line instead of the throughput line)")
     ap.add_argument("--ablation-steps", type=int, default=1000)
     ap.add_argument("--ablation-oracle-steps", type=int, default=10)
-    ap.add_argument("--blast3d", action="store_true",
-                    help="also time the 3D blast (256^3 grid, 134M particles) and report it beside the line")
+    ap.add_argument("--no-blast3d", action="store_true",
+                    help="skip the 3D blast leg (256^3 grid, 134M particles), reported beside the line")
     ap.add_argument("--blast-n", type=int, default=256)
     ap.add_argument("--blast-steps", type=int, default=100)
-    ap.add_argument("--blast-warmup", type=int, default=5)
+    ap.add_argument("--blast-warmup", type=int, default=16)
     ap.add_argument("--blast-fp64", action="store_true",
                     help="also time the 3D blast with the plain FP64 state")
-    ap.add_argument("--blast-oracle-steps", type=int, default=0,
-                    help="oracle steps of the 64^3 downscale for the accuracy figure (0 = skip)")
+    ap.add_argument("--blast-oracle-steps", type=int, default=4,
+                    help="oracle steps of the 64^3 downscale for the accuracy figure, on all host "
+                         "cores (0 = skip)")
     ap.add_argument("--all-precisions", action="store_true",
                     help="also time the FP32 state with FP64 and with FP32 accumulators on the same workload")
     ap.add_argument("--aerofoil", action="store_true",
@@ -395,6 +434,8 @@ def main():
         fp64 = time_gpu(pb, G.FP64, args.steps, args.warmup, args.profile_steps)
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/step, {fp64['value']:.4e} particle-steps/s")
 
+    blast3d_leg = None if args.no_blast3d else blast3d(args)
+
     # the other two FP32-state modes (FP64 and FP32 accumulators) on the same
     # workload and span, for the precision ablation
     modes = None
@@ -412,22 +453,27 @@ def main():
     ntiles = ((pb.n[0] + 15) // 16) * ((pb.n[1] + 15) // 16)
     ncells = ntiles * 256
     bytes_fix = sweep_bytes(pb, nnodes, ncells, 4, 8)
+    bytes_scope = survey_bytes(2, N, nnodes)
     sw = fix["sweeps_ms"]
     # The tile-scan slot holds no kernel at this size (at most 4096 tiles):
-    # its event pair times the profiling overhead alone, taken off the
-    # dominant sweep's time
+    # its event pair times the profiling overhead alone, taken off each
+    # sweep's time
     overhead = sw.get("tilescan", 0.0) if ntiles <= 4096 else 0.0
     dominant = max(sw, key=sw.get) if sw else "update"
     dom_ms = sw.get(dominant, float("nan")) - overhead
-    achieved = bytes_fix[dominant] / (dom_ms * 1e-3) / 1e9
-    # every sweep with algorithmic bytes, for comparison with the dominant one
+    # achieved = the scope's algorithmic bytes of the dominant sweep per
+    # launch / its kernel time; the implementation's own count beside it
+    achieved = bytes_scope.get(dominant, bytes_fix[dominant]) / (dom_ms * 1e-3) / 1e9
+    achieved_impl = bytes_fix[dominant] / (dom_ms * 1e-3) / 1e9
     sweeps_roofline = {}
     for k in ("p2g", "g2p_p2g", "cellscan", "update"):
         if k in sw and bytes_fix[k] > 0:
             kms = sw[k] - overhead
-            gbps = bytes_fix[k] / (kms * 1e-3) / 1e9
-            sweeps_roofline[k] = {"kernel_ms": round(kms, 5), "algorithmic_MB": round(bytes_fix[k] / 1e6, 2),
-                                  "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+            b = bytes_scope.get(k, bytes_fix[k])
+            gbps = b / (kms * 1e-3) / 1e9
+            sweeps_roofline[k] = {"kernel_ms": round(kms, 5), "algorithmic_MB": round(b / 1e6, 2),
+                                  "GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                                  "impl_MB": round(bytes_fix[k] / 1e6, 2)}
     src_hash = kernel_source_hash()
     counters = measured_counters(dominant, pb.name, src_hash)
     traffic = counters.get("bytes_per_launch")
@@ -436,40 +482,61 @@ def main():
     valu = counters.get("sq_insts_valu")
     valu_frac = round(valu * 4 / (1024 * 2.4e9 * dom_ms * 1e-3), 3) if valu else None
     step_bytes = sum(bytes_fix.values())
+    step_scope = sum(bytes_scope.values())
+    # self-check: the timed step against the sum of its sweeps' kernel times
+    sweep_sum = sum(v - overhead for k, v in sw.items() if k != "tilescan" or ntiles > 4096) if sw else None
     copy_gbps = copy_bandwidth()
     log(f"device copy: {copy_gbps} GB/s")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": dominant, "kernel_ms": round(dom_ms, 5),
+                "algorithmic_bytes_per_launch": int(bytes_scope.get(dominant, bytes_fix[dominant])),
+                "impl_bytes_per_launch": int(bytes_fix[dominant]),
+                "frac_impl_bytes": round(achieved_impl / HBM_PEAK_GBPS, 4),
                 "event_overhead_ms": round(overhead, 5),
                 "measured_copy_GBps": copy_gbps,
                 "valu_issue_frac": valu_frac,
-                "algorithmic_bytes_per_launch": int(bytes_fix[dominant]),
-                "step_algorithmic_bytes": int(step_bytes),
-                "step_achieved_GBps": round(step_bytes / (fix["ms_per_step"] * 1e-3) / 1e9, 1)}
+                "step_algorithmic_bytes": int(step_scope),
+                "step_achieved_GBps": round(step_scope / (fix["ms_per_step"] * 1e-3) / 1e9, 1),
+                "step_impl_bytes": int(step_bytes),
+                "step_ms_over_sweep_sum": round(fix["ms_per_step"] / sweep_sum, 4) if sweep_sum else None}
 
     cpu = None
     accuracy = None
     if not args.no_cpu and args.cpu_steps > 0:
+        # The oracle on a bounded sample of the same problem: its first
+        # --cpu-steps steps, once on one host thread (the reference order) and
+        # once on every host core (OpenMP; per-thread P2G sums added in
+        # thread order).
         from oracle import oracle as O
         O.build(force=False)
-        t0 = time.perf_counter()
-        o = O.Oracle(pb)
-        t1 = time.perf_counter()
-        o.step(args.cpu_steps)
-        t2 = time.perf_counter()
-        cpu = {"value": round(N * args.cpu_steps / (t2 - t1), 1), "unit": "particle-steps/s",
-               "cores": 1, "kind": "oracle", "host_cpus": os.cpu_count(),
+        ncpu = os.cpu_count() or 1
+        legs = {}
+        rho_o = None
+        for threads in sorted({1, ncpu}):
+            t0 = time.perf_counter()
+            o = O.Oracle(pb, threads=threads)
+            t1 = time.perf_counter()
+            o.step(args.cpu_steps)
+            t2 = time.perf_counter()
+            legs[threads] = {"value": round(N * args.cpu_steps / (t2 - t1), 1), "seconds": round(t2 - t1, 2),
+                             "setup_s": round(t1 - t0, 2)}
+            if threads == 1:
+                rho_o = o.particles(O.F_RHO)
+            o.close()
+            log(f"cpu oracle, {threads} thread(s): {legs[threads]['value']:.3e} particle-steps/s over {t2 - t1:.1f} s")
+        best = max(legs, key=lambda k: legs[k]["value"])
+        cpu = {"value": legs[best]["value"], "unit": "particle-steps/s", "cores": best, "kind": "oracle",
+               "host_cpus": ncpu, "single_thread": legs[1]["value"],
+               "threads": {str(k): v for k, v in legs.items()},
                "sample": f"first {args.cpu_steps} steps of the same {pb.name} problem "
-                         f"({N} particles), sequential FP64 C, one host thread; setup {t1 - t0:.1f} s excluded"}
-        log(f"cpu oracle: {cpu['value']:.3e} particle-steps/s over {t2 - t1:.1f} s")
-        rho_o = o.particles(O.F_RHO)
+                         f"({N} particles), FP64 C oracle on {best} host thread(s) (OpenMP; one-thread "
+                         f"figure beside it); setup excluded"}
         l1 = lambda r: float(np.abs(r - rho_o).sum() / np.abs(rho_o).sum())
         accuracy = {"steps": args.cpu_steps,
                     "rel_l1_density_fp32_fix64": l1(run_sample_gpu(pb, G.FP32_FIX64, args.cpu_steps))}
         if not args.no_fp64:
             accuracy["rel_l1_density_fp64"] = l1(run_sample_gpu(pb, G.FP64, args.cpu_steps))
-        o.close()
 
     serving = None
     if args.serve_requests > 0:
@@ -507,6 +574,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(fix["ms_per_step"], 5),
+        "graph_setup_ms": fix["graph_setup_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -519,6 +587,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64": None if fp64 is None else {"value": round(fp64["value"], 1),
                                           "ms_per_step": round(fp64["ms_per_step"], 5),
+                                          "graph_setup_ms": fp64["graph_setup_ms"],
                                           "sweeps_ms": fp64["sweeps_ms"]},
         "sweeps_ms": sw,
         "sweeps_roofline": sweeps_roofline,
@@ -526,7 +595,7 @@ def main():
         "serving": serving,
         "host_inclusive": hostinc,
         "precision_modes": modes,
-        "blast3d": blast3d(args) if args.blast3d else None,
+        "blast3d": blast3d_leg,
         "aerofoil": aerofoil(args) if args.aerofoil else None,
         "kernel_source_hash": src_hash,
     }

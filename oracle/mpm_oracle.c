@@ -7,12 +7,23 @@
  * Where the paper is silent or ambiguous the reading taken is stated at the
  * point of use.  No blocking, fusion or reordering: every operator is a
  * separate loop over particles (in id order) or over nodes.
+ *
+ * Threads (orc_set_threads; default 1, the reference order): the loops over
+ * particles and over nodes are independent per iteration and may run on
+ * several OpenMP threads.  The only sums across particles are the two P2G
+ * scatters; with more than one thread each thread scatters a contiguous
+ * block of ids into its own node arrays, and those are added in thread
+ * order, so the result differs from one thread by FP64 rounding only.  Used
+ * to time the CPU baseline on all host cores and to shorten long runs.
  */
 #include "oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 struct orc_state {
     orc_problem pb;
@@ -32,6 +43,8 @@ struct orc_state {
     int64_t step;
     int64_t wall_escapes;
     int failed;
+    int nthreads;          /* OpenMP threads of the loops (1: sequential)   */
+    double *priv;          /* nthreads * (1 + 2 dim) node arrays (P2G sums) */
 };
 
 /* ---------------------------------------------------------------- basis -- */
@@ -282,6 +295,7 @@ void orc_destroy(orc_state *s) {
     }
     for (int c = 0; c < 9; ++c) free(s->G[c]);
     free(s->M); free(s->rho); free(s->E); free(s->obst); free(s->m);
+    free(s->priv);
     free(s);
 }
 
@@ -326,6 +340,7 @@ int orc_create(const orc_problem *pb, int64_t np,
         s->nnodes *= s->nn[a];
     }
     s->np = np;
+    s->nthreads = 1;
     size_t pbytes = (size_t)(np > 0 ? np : 1) * sizeof(double);
     size_t nbytes = (size_t)s->nnodes * sizeof(double);
     for (int a = 0; a < 3; ++a) {
@@ -425,11 +440,93 @@ int orc_set_dt(orc_state *s, double dt) {
     return ORC_OK;
 }
 
+int orc_set_threads(orc_state *s, int n) {
+    if (!s || n < 1) return ORC_E_ARG;
+#ifndef _OPENMP
+    if (n > 1) return ORC_E_ARG;
+#endif
+    free(s->priv);
+    s->priv = NULL;
+    if (n > 1) {
+        s->priv = (double *)malloc((size_t)n * (1 + 2 * s->pb.dim) * s->nnodes * sizeof(double));
+        if (!s->priv) { s->nthreads = 1; return ORC_E_ARG; }
+    }
+    s->nthreads = n;
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------- one step -- */
 
 /* Nodal value u/m, zero where the node carries no mass (reading: nodes with
  * m <= 0 do not contribute to G2P and G2PD). */
 static double ratio(double u, double m) { return m > 0.0 ? u / m : 0.0; }
+
+/* The P2G sums of particles k0 .. k1-1, in id order, added into out:
+ * which = 0: mass, momentum and internal force (step (ii)), out = m, p[3],
+ * f[3]; which = 1: the updated momentum M V' (step (vi)), out = p2[3]. */
+static void scatter_range(const orc_state *s, int which, int64_t k0, int64_t k1, double *const *out) {
+    const orc_problem *pb = &s->pb;
+    const int dim = pb->dim;
+    const double gam = pb->gamma;
+    stencil st;
+    for (int64_t k = k0; k < k1; ++k) {
+        double pt[3] = {s->x[0][k], s->x[1][k], dim == 3 ? s->x[2][k] : 0.0};
+        point_stencil(pb, s->h, s->nn, pt, &st);
+        if (which == 1) {
+            for (int c = 0; c < st.count; ++c)
+                for (int a = 0; a < dim; ++a)
+                    out[a][st.node[c]] += s->M[k] * s->v[a][k] * st.w[c];
+            continue;
+        }
+        double P = eos_pressure(gam, s->rho[k], s->E[k]);
+        double Q = particle_q(s, k, P);
+        double vol = s->M[k] / s->rho[k];
+        for (int c = 0; c < st.count; ++c) {
+            int64_t i = st.node[c];
+            out[0][i] += s->M[k] * st.w[c];
+            for (int a = 0; a < dim; ++a) {
+                out[1 + a][i] += s->M[k] * s->v[a][k] * st.w[c];
+                out[1 + dim + a][i] += (P + Q) * vol * st.dw[c][a];
+            }
+        }
+    }
+}
+
+/* One P2G over all particles into out (the arrays of scatter_range,
+ * zeroed by the caller): with one thread in id order; with several,
+ * per-thread node arrays over contiguous id blocks, then added in thread
+ * order. */
+static void scatter(orc_state *s, int which, double *const *out) {
+    const int dim = s->pb.dim;
+    const int nq = which == 0 ? 1 + 2 * dim : dim;
+    const int64_t NN = s->nnodes;
+    if (s->nthreads <= 1) {
+        scatter_range(s, which, 0, s->np, out);
+        return;
+    }
+#pragma omp parallel num_threads(s->nthreads)
+    {
+#ifdef _OPENMP
+        const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#else
+        const int t = 0, nt = 1;
+#endif
+        double *mine[7];
+        for (int q = 0; q < nq; ++q) {
+            mine[q] = s->priv + ((size_t)t * nq + q) * NN;
+            memset(mine[q], 0, (size_t)NN * sizeof(double));
+        }
+        scatter_range(s, which, s->np * t / nt, s->np * (t + 1) / nt, mine);
+#pragma omp barrier
+#pragma omp for
+        for (int64_t i = 0; i < NN; ++i)
+            for (int q = 0; q < nq; ++q) {
+                double sum = 0.0;
+                for (int u = 0; u < nt; ++u) sum += s->priv[((size_t)u * nq + q) * NN + i];
+                out[q][i] = sum;
+            }
+    }
+}
 
 static int one_step(orc_state *s) {
     const orc_problem *pb = &s->pb;
@@ -437,7 +534,7 @@ static int one_step(orc_state *s) {
     const double dt = s->dt;
     const double gam = pb->gamma;
     const int64_t NN = s->nnodes;
-    stencil st;
+    const int nt = s->nthreads;
 
     /* (i) Grid reset: all accumulators start from zero. */
     memset(s->m, 0, (size_t)NN * sizeof(double));
@@ -449,23 +546,14 @@ static int one_step(orc_state *s) {
 
     /* (ii) P2G of mass and momentum, P2GD of the internal force
      * f_i = sum_k (P_k + Q_k) (M_k / rho_k) grad phi_i (eq. mxa=f). */
-    for (int64_t k = 0; k < s->np; ++k) {
-        double pt[3] = {s->x[0][k], s->x[1][k], dim == 3 ? s->x[2][k] : 0.0};
-        point_stencil(pb, s->h, s->nn, pt, &st);
-        double P = eos_pressure(gam, s->rho[k], s->E[k]);
-        double Q = particle_q(s, k, P);
-        double vol = s->M[k] / s->rho[k];
-        for (int c = 0; c < st.count; ++c) {
-            int64_t i = st.node[c];
-            s->m[i] += s->M[k] * st.w[c];
-            for (int a = 0; a < dim; ++a) {
-                s->p[a][i] += s->M[k] * s->v[a][k] * st.w[c];
-                s->f[a][i] += (P + Q) * vol * st.dw[c][a];
-            }
-        }
+    {
+        double *out[7] = {s->m};
+        for (int a = 0; a < dim; ++a) { out[1 + a] = s->p[a]; out[1 + dim + a] = s->f[a]; }
+        scatter(s, 0, out);
     }
 
     /* (iii) Boundary conditions on momentum and force. */
+#pragma omp parallel for num_threads(nt) if (nt > 1)
     for (int64_t i = 0; i < NN; ++i) {
         double u[3] = {0, 0, 0}, fv[3] = {0, 0, 0};
         for (int a = 0; a < dim; ++a) { u[a] = s->p[a][i]; fv[a] = s->f[a][i]; }
@@ -485,7 +573,9 @@ static int one_step(orc_state *s) {
             s->vn[a][i] = ratio(s->pu[a][i], s->m[i]);
             s->an[a][i] = ratio(s->fbc[a][i], s->m[i]);
         }
+#pragma omp parallel for num_threads(nt) if (nt > 1)
     for (int64_t k = 0; k < s->np; ++k) {
+        stencil st;
         double pt[3] = {s->x[0][k], s->x[1][k], dim == 3 ? s->x[2][k] : 0.0};
         point_stencil(pb, s->h, s->nn, pt, &st);
         double vb[3] = {0, 0, 0}, A[3] = {0, 0, 0};
@@ -500,15 +590,10 @@ static int one_step(orc_state *s) {
         for (int a = 0; a < dim; ++a) s->v[a][k] += dt * s->acc[a][k];
 
     /* (vi) P2G of the updated momentum M V'. */
-    for (int64_t k = 0; k < s->np; ++k) {
-        double pt[3] = {s->x[0][k], s->x[1][k], dim == 3 ? s->x[2][k] : 0.0};
-        point_stencil(pb, s->h, s->nn, pt, &st);
-        for (int c = 0; c < st.count; ++c)
-            for (int a = 0; a < dim; ++a)
-                s->p2[a][st.node[c]] += s->M[k] * s->v[a][k] * st.w[c];
-    }
+    scatter(s, 1, s->p2);
 
     /* (vii) Boundary conditions on the re-mapped momentum. */
+#pragma omp parallel for num_threads(nt) if (nt > 1)
     for (int64_t i = 0; i < NN; ++i) {
         double u[3] = {0, 0, 0};
         for (int a = 0; a < dim; ++a) u[a] = s->p2[a][i];
@@ -522,7 +607,9 @@ static int one_step(orc_state *s) {
     for (int a = 0; a < dim; ++a)
         for (int64_t i = 0; i < NN; ++i) s->v2n[a][i] = ratio(s->p2[a][i], s->m[i]);
     int bad = 0;
+#pragma omp parallel for num_threads(nt) if (nt > 1) reduction(| : bad)
     for (int64_t k = 0; k < s->np; ++k) {
+        stencil st;
         double pt[3] = {s->x[0][k], s->x[1][k], dim == 3 ? s->x[2][k] : 0.0};
         point_stencil(pb, s->h, s->nn, pt, &st);
         double G[9] = {0};
@@ -542,6 +629,8 @@ static int one_step(orc_state *s) {
      * Outflow: the particle re-enters at the inflow face, its transverse
      * coordinates drawn from a counter hash of (seed, step, id), with the
      * inflow state.  Reading of "a random cell at the inflow boundary". */
+    int64_t escapes = 0;
+#pragma omp parallel for num_threads(nt) if (nt > 1) reduction(+ : escapes)
     for (int64_t k = 0; k < s->np; ++k) {
         for (int a = 0; a < dim; ++a) s->x[a][k] += dt * s->vbar[a][k];
         int recycled = 0;
@@ -561,19 +650,22 @@ static int one_step(orc_state *s) {
             recycled = 1;
         }
         if (!recycled) {
-            /* Any other exit is prevented by the CFL bound; clamp and count. */
+            /* Any other exit is prevented by the CFL bound; clamp the
+             * particle back inside and count the event once. */
+            int escaped = 0;
             for (int a = 0; a < dim; ++a) {
                 double L = pb->hi[a] - pb->lo[a];
-                if (s->x[a][k] < pb->lo[a]) { s->x[a][k] = pb->lo[a]; s->wall_escapes++; }
-                else if (s->x[a][k] >= pb->hi[a]) {
-                    s->x[a][k] = pb->hi[a] - 1e-9 * L; s->wall_escapes++;
-                }
+                if (s->x[a][k] < pb->lo[a]) { s->x[a][k] = pb->lo[a]; escaped = 1; }
+                else if (s->x[a][k] >= pb->hi[a]) { s->x[a][k] = pb->hi[a] - 1e-9 * L; escaped = 1; }
             }
+            escapes += escaped;
         }
     }
+    s->wall_escapes += escapes;
 
     /* (xi)-(xii) CFL from |V'|, |Vbar| and the updated sound speed; advance t. */
     double vmax = 0.0, cmax = 0.0;
+#pragma omp parallel for num_threads(nt) if (nt > 1) reduction(max : vmax, cmax) reduction(| : bad)
     for (int64_t k = 0; k < s->np; ++k) {
         double a1 = 0.0, a2 = 0.0;
         for (int a = 0; a < dim; ++a) {

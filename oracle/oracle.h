@@ -79,6 +79,12 @@ int orc_step(orc_state *s, int64_t n_steps);
  * with the same dt).  Returns ORC_E_ARG if dt <= 0. */
 int orc_set_dt(orc_state *s, double dt);
 
+/* Run the loops on n OpenMP threads (default 1).  With n > 1 the two P2G
+ * scatters add per-thread partial node sums in thread order, so results
+ * differ from one thread by FP64 rounding only.  ORC_E_ARG if n < 1, or
+ * n > 1 in a build without OpenMP. */
+int orc_set_threads(orc_state *s, int n);
+
 /* Particle fields in id order, one double array of np per component. */
 #define ORC_F_X    0   /* dim components */
 #define ORC_F_V    1   /* dim */

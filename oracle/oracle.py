@@ -41,9 +41,10 @@ class _Problem(C.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain C99, -O2, no fast-math)."""
+    """Compile liboracle.so with gcc (plain C99, -O2, no fast-math; OpenMP
+    for the optional multi-threaded loops)."""
     if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-Wall",
+        cmd = ["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
                "-o", LIB_PATH] + SOURCES + ["-lm"]
         subprocess.run(cmd, check=True)
     return LIB_PATH
@@ -66,6 +67,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_set_dt.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
         L.orc_get_particles.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_get_grid.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
@@ -114,9 +116,11 @@ class OracleError(RuntimeError):
 
 
 class Oracle:
-    """One oracle simulation built from a workload problem."""
+    """One oracle simulation built from a workload problem.  `threads` > 1
+    runs its loops on that many OpenMP threads (the P2G sums then differ from
+    the single-thread order by FP64 rounding)."""
 
-    def __init__(self, pb):
+    def __init__(self, pb, threads: int = 1):
         L = lib()
         self.pb = pb
         self.dim = pb.dim
@@ -161,6 +165,12 @@ class Oracle:
         L.orc_grid_shape(self._h, shp)
         self.nodes = tuple(int(v) for v in shp)
         self.nnodes = int(np.prod(self.nodes))
+        self.threads = 1
+        if threads > 1:
+            rc = L.orc_set_threads(self._h, int(threads))
+            if rc:
+                raise OracleError(rc, "orc_set_threads")
+            self.threads = int(threads)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -27,7 +27,11 @@ using namespace mpm;
 
 namespace {
 
-constexpr int kGraphSteps = 16;      // steps per captured graph
+constexpr int kGraphSteps = 16;      // steps per replay of the largest captured graph
+// Captured graphs of a handle: 16, 8, 4, 2 and 1 steps, so that any step
+// count is a run of graph replays (the binary digits of the remainder).
+constexpr int kGraphLevels = 5;
+constexpr int graph_steps(int level) { return kGraphSteps >> level; }
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -184,8 +188,8 @@ struct mpm_handle {
     ProbDev *dev;          // device descriptor (workspace start)
     char *ws;
     int reported_err;
-    // graph cache for single-problem stepping
-    hipGraphExec_t gexec;
+    // graphs of single-problem stepping, captured by the first mpm_step
+    hipGraphExec_t gexec[kGraphLevels];
     hipStream_t cap;
 };
 
@@ -505,26 +509,32 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
     make_tables(one, 1, tiles, single);
     const bool to_end = n_steps <= 0;
     if (to_end && !(h->host.t_end > 0)) return MPM_E_ARG;
+    // The first call captures the step graphs (16, 8, 4, 2 and 1 steps);
+    // every later call, of any step count, is graph replays only.  The
+    // kernels read the per-step state from the device descriptor, so the
+    // graphs are reusable.
+    if (!h->gexec[0]) {
+        if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return MPM_E_HIP;
+        for (int lv = 0; lv < kGraphLevels; ++lv) {
+            hipGraph_t g;
+            if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_E_HIP;
+            enqueue_steps(one, 1, graph_steps(lv), h->cap);
+            if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return MPM_E_HIP;
+            const hipError_t e = hipGraphInstantiate(&h->gexec[lv], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->gexec[lv] = nullptr;
+                for (int j = 0; j < lv; ++j) { (void)hipGraphExecDestroy(h->gexec[j]); h->gexec[j] = nullptr; }
+                return MPM_E_HIP;
+            }
+        }
+    }
     const long long armed = to_end ? (1LL << 60) : n_steps;
     launch_arm(single, &armed, s);
-    // Replays of a captured graph of kGraphSteps steps; the kernels read the
-    // per-step state from the device descriptor, so the graph is reusable.
-    if (!h->gexec && (to_end || n_steps >= kGraphSteps)) {
-        hipGraph_t g;
-        if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return MPM_E_HIP;
-        if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_E_HIP;
-        enqueue_steps(one, 1, kGraphSteps, h->cap);
-        if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return MPM_E_HIP;
-        if (hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return MPM_E_HIP;
-        }
-        (void)hipGraphDestroy(g);
-    }
     if (to_end) {
         for (;;) {
             for (int r = 0; r < 4; ++r)
-                if (hipGraphLaunch(h->gexec, s) != hipSuccess) return MPM_E_HIP;
+                if (hipGraphLaunch(h->gexec[0], s) != hipSuccess) return MPM_E_HIP;
             ProbDev cur;
             if (read_dynamic(h, &cur, s)) return MPM_E_HIP;
             if (!cur.active) break;
@@ -532,12 +542,12 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
         return MPM_OK;
     }
     long long left = n_steps;
-    while (left >= kGraphSteps && h->gexec) {
-        if (hipGraphLaunch(h->gexec, s) != hipSuccess) return MPM_E_HIP;
-        left -= kGraphSteps;
-    }
-    enqueue_steps(one, 1, (int)left, s);
-    return hip_ok(hipGetLastError());
+    for (; left >= kGraphSteps; left -= kGraphSteps)
+        if (hipGraphLaunch(h->gexec[0], s) != hipSuccess) return MPM_E_HIP;
+    for (int lv = 1; lv < kGraphLevels; ++lv)
+        if (left & graph_steps(lv))
+            if (hipGraphLaunch(h->gexec[lv], s) != hipSuccess) return MPM_E_HIP;
+    return MPM_OK;
 }
 
 int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last, int64_t *step,
@@ -711,7 +721,8 @@ int mpm_grid_shape(const mpm_handle *h, int32_t nodes[3]) {
 
 int mpm_destroy(mpm_handle *h) {
     if (!h) return MPM_E_ARG;
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    for (int lv = 0; lv < kGraphLevels; ++lv)
+        if (h->gexec[lv]) (void)hipGraphExecDestroy(h->gexec[lv]);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     free(h);
     return MPM_OK;
