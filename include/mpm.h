@@ -4,19 +4,24 @@
  * Capone, de Falco, "Portable, massively parallel implementation of a
  * Material Point Method for compressible flows" (arXiv 2404.17057).
  *
- * One time step (Sec. 3, steps (i)-(xii); Algorithm 1 "Time loop sketch"):
- *   cell sort of the particles (step (xi), optional re-ordering, here every step)
- *   P2G of mass and momentum, P2GD of the internal force (step (ii); eqs.
+ * One time step (Sec. 3, step 3, sub-steps (i)-(xiv); Algorithm 1 "Time loop
+ * sketch"):
+ *   P2G of mass and momentum, P2GD of the internal force ((ii); eqs.
  *     p2g_gen, p2gd_gen, mxa=f)
- *   obstacle, wall and inflow conditions on momentum and force (step (iii);
- *     eqs. normali1, normali2; wind-tunnel conditions of Sec. 4.1)
- *   grid momentum update (step (iv))
- *   G2P of velocity and acceleration, FLIP velocity update (step (v); eq. g2p_gen)
- *   P2G of the updated momentum and its boundary conditions (steps (vi)-(vii))
- *   G2PD velocity gradient, energy, density and pressure update (step (viii);
+ *   obstacle, wall and inflow conditions on momentum and force ((iii); eqs.
+ *     normali1, normali2; wind-tunnel conditions of Sec. 4.1)
+ *   grid momentum update ((iv))
+ *   G2P of velocity and acceleration, FLIP velocity update ((v); eq. g2p_gen)
+ *   P2G of the updated momentum and its boundary conditions ((vi)-(vii))
+ *   G2PD velocity gradient, energy, density and pressure update ((viii);
  *     eq. g2pd_gen; ideal-gas state equation and artificial viscosity, eq. muart)
- *   postponed move with the G2P velocity (step (ix)), outflow recycling (Sec. 4.1)
- *   CFL time step from particle velocities and sound speed (step (xi); Sec. 2.2, CFL)
+ *   postponed move with the G2P velocity ((ix)), outflow recycling (Sec. 4.1)
+ *   particle-to-cell map ((x)) and re-ordering ((xii), optional in the
+ *     paper, here a cell sort every step)
+ *   CFL time step from particle velocities and sound speed ((xiii)-(xiv);
+ *     Sec. 2.2, eq. CFL)
+ * Sub-step (i), the grid reset, is the zero start of every P2G sum; (xi),
+ * intermediate output, is mpm_read_fields between runs.
  *
  * Conventions
  *   - Every call returns an int status (MPM_OK or a negative MPM_E_* code);
@@ -24,15 +29,20 @@
  *   - Device memory: the caller owns one device workspace of at least
  *     mpm_footprint() bytes per problem and keeps it alive until
  *     mpm_destroy().  The library allocates no device memory on the stepping
- *     path (mpm_read_grid and mpm_step_batch's graph cache excepted, see there).
+ *     path; mpm_read_grid allocates a temporary buffer (mpm_read_grid_noalloc
+ *     does not), and mpm_step_batch keeps one small device table of its
+ *     captured graphs per process and device.
  *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the
  *     default stream).  All work is enqueued on it; mpm_step and
  *     mpm_step_batch return without waiting.
  *   - The handle is owned by the library and is not thread-safe.
  *   - Errors detected on the device (J = 1 + dt div v <= 0, non-finite
- *     state, fixed-point overflow, a particle leaving through a wall) are
- *     sticky: the problem stops advancing and the next mpm_status /
- *     mpm_read_fields returns the code.
+ *     state, fixed-point overflow) are sticky: the problem stops advancing
+ *     and the next mpm_status / mpm_read_fields returns the code; after that
+ *     mpm_step returns MPM_E_STATE.
+ *   - A particle that a step would move out through a wall (which the CFL
+ *     bound excludes) is put back inside, on the wall or just below the
+ *     high face, and counted in mpm_counters()[1]; it is not an error.
  */
 #ifndef MPM_H
 #define MPM_H
@@ -143,40 +153,54 @@ typedef struct {
 
 typedef struct mpm_handle mpm_handle;
 
-/* Device bytes one problem needs in its workspace.  Errors: MPM_E_ARG. */
+/* Device bytes one problem needs in its workspace (particle state of two
+ * step parities, grid accumulators, sort tables; Sec. 3 step 2 keeps all of
+ * it on the device for the whole run).  Errors: MPM_E_ARG. */
 int mpm_footprint(const mpm_desc *desc, size_t *device_bytes);
 
-/* Build a problem in the caller's workspace (device pointer, 256-byte
- * aligned, >= mpm_footprint bytes): copies the particles to the device
- * (one host-to-device transfer, converted to the state precision), sets up
- * boundary flags and normals, fixed-point quanta, the first cell sort and
- * the first time step.  Synchronises `hip_stream` before returning.
+/* Sec. 3 step 2 (the method's object is constructed once and its grid and
+ * particle data copied to the device once; the inputs are generated
+ * separately, step 1): build a problem in the caller's workspace (device
+ * pointer, 256-byte aligned, >= mpm_footprint bytes).  Copies the particles
+ * to the device (one host-to-device transfer, converted to the state
+ * precision), sets up the static node flags and obstacle normals (the
+ * boundary markers and unit normals of step 1 and Sec. 2.2, eq. sdf), the
+ * fixed-point quanta, the first cell sort and the first time step (eq. CFL
+ * from |V| and the sound speed of the initial state).  Synchronises
+ * `hip_stream` before returning.  The host arrays are only read.
  * Errors: MPM_E_ARG (descriptor, ids not a permutation, particle outside
  * the box, non-positive mass or density), MPM_E_WORKSPACE, MPM_E_HIP. */
 int mpm_init(const mpm_desc *desc, const mpm_particles_host *particles,
              const mpm_obstacle_host *obstacle, void *dev_workspace,
              size_t workspace_bytes, void *hip_stream, mpm_handle **out);
 
-/* Enqueue n_steps time steps (asynchronous).  Steps after t_end (t_end > 0)
- * or after a device error are skipped on the device.  n_steps <= 0 runs to
- * t_end (requires t_end > 0; synchronises once per 64 steps to check).
- * Errors: MPM_E_ARG, MPM_E_STATE (a device error was already reported),
- * MPM_E_HIP. */
+/* Sec. 3 step 3, the time advancing loop (sub-steps (i)-(xiv) above;
+ * Algorithm 1): enqueue n_steps time steps (asynchronous).  Steps after
+ * t_end (t_end > 0) or after a device error are skipped on the device.
+ * n_steps <= 0 runs to t_end (requires t_end > 0; synchronises once per 64
+ * steps to check).  The first call on a handle captures its step graphs
+ * (16, 8, 4, 2 and 1 steps; host work of a few milliseconds, before
+ * anything is enqueued); every call replays them.  Errors: MPM_E_ARG,
+ * MPM_E_STATE (a device error was already reported), MPM_E_HIP. */
 int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream);
 
-/* Advance several problems together: every sweep of the step is one launch
- * whose workgroups cover the tiles of all problems (continuous batching).
- * Problems must share dim, shape and precision (else MPM_E_UNSUPPORTED).
- * n_steps[i] steps for problem i; problems that finish early idle.  Up to
- * 64 problems per call.  Asynchronous.  Errors: MPM_E_ARG,
- * MPM_E_UNSUPPORTED, MPM_E_STATE, MPM_E_HIP. */
+/* The loop of mpm_step for several independent problems at once (the
+ * serving form; the paper runs one problem): every sweep of a step is one
+ * launch whose workgroups cover the tiles of all problems.  Problems must
+ * share dim, shape and precision (else MPM_E_UNSUPPORTED).  n_steps[i]
+ * steps for problem i (>= 0); problems that finish early idle.  Up to 64
+ * problems per call.  Asynchronous.  Errors: MPM_E_ARG, MPM_E_UNSUPPORTED,
+ * MPM_E_STATE, MPM_E_HIP. */
 int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps,
                    void *hip_stream);
 
-/* Particle fields, returned as double in id order.  Bit i of field_mask
- * selects field i below; host_out[j] receives the j-th selected field, a
- * buffer of n_particles * ncomp doubles, component-major.  Synchronises the
- * stream.  Returns the sticky device error, if any, after copying. */
+/* Sec. 3 step 3 (xi) and step 4 (device-to-host copy of the particle
+ * state, at intermediate moments and at the end): particle fields, returned
+ * as double in id order.  Bit i of field_mask selects field i below;
+ * host_out[j] receives the j-th selected field, a caller-owned buffer of
+ * n_particles * ncomp doubles, component-major.  Synchronises the stream.
+ * Errors: MPM_E_ARG (mask bit beyond MPM_F_ID, a NULL buffer), MPM_E_HIP;
+ * otherwise the sticky device error, if any, after copying. */
 enum {
     MPM_F_X = 0,    /* dim components                                */
     MPM_F_V = 1,    /* dim                                           */
@@ -210,11 +234,12 @@ enum { MPM_G_M = 0, MPM_G_P = 1, MPM_G_F = 2, MPM_G_PUPD = 3, MPM_G_P2 = 4,
        MPM_G_FBC = 5, MPM_G_FLAGS = 6 };
 int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);
 
-/* Time, next and last time step, completed steps and FP64 sums over the
- * particles: mass, momentum (3), internal energy sum M e, kinetic energy
- * sum M |v|^2 / 2, as of the last completed step (with `conserved`, one
- * small kernel on the stream reduces them from that step's per-tile sums).
- * Synchronises the stream.  Any pointer may be NULL.
+/* Sec. 3 (xiii)-(xiv) (the time step and the time it advances to) and the
+ * checks of a run: time, next and last time step, completed steps and FP64
+ * sums over the particles: mass, momentum (3), internal energy sum M e,
+ * kinetic energy sum M |v|^2 / 2, as of the last completed step (with
+ * `conserved`, one small kernel on the stream reduces them from that step's
+ * per-tile sums).  Synchronises the stream.  Any pointer may be NULL.
  * Returns the sticky device error (MPM_E_NONPHYSICAL / MPM_E_OVERFLOW),
  * else MPM_OK. */
 int mpm_status(mpm_handle *h, double *t, double *dt_next, double *dt_last,

@@ -3,7 +3,7 @@
  *
  * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written from Sec. 2.2 (basis,
  * lumped mass, P2G / G2P / P2GD / G2PD operators, obstacle projection, CFL),
- * Sec. 3 (steps (i)-(xii) of the time loop) and Algorithm 1 of the paper.
+ * Sec. 3 (steps (i)-(xiv) of the time loop) and Algorithm 1 of the paper.
  * Where the paper is silent or ambiguous the reading taken is stated at the
  * point of use.  No blocking, fusion or reordering: every operator is a
  * separate loop over particles (in id order) or over nodes.
@@ -417,7 +417,7 @@ int orc_create(const orc_problem *pb, int64_t np,
         }
     }
 
-    /* First time step from the initial state (Sec. 2.2, CFL; Sec. 3 (xi)). */
+    /* First time step from the initial state (Sec. 2.2, CFL; Sec. 3 (xiii)). */
     double vmax = 0.0, cmax = 0.0;
     for (int64_t k = 0; k < np; ++k) {
         double vv = 0.0;
@@ -663,7 +663,7 @@ static int one_step(orc_state *s) {
     }
     s->wall_escapes += escapes;
 
-    /* (xi)-(xii) CFL from |V'|, |Vbar| and the updated sound speed; advance t. */
+    /* (xiii)-(xiv) CFL from |V'|, |Vbar| and the updated sound speed; advance t. */
     double vmax = 0.0, cmax = 0.0;
 #pragma omp parallel for num_threads(nt) if (nt > 1) reduction(max : vmax, cmax) reduction(| : bad)
     for (int64_t k = 0; k < s->np; ++k) {

@@ -5,7 +5,7 @@
  * (arXiv 2404.17057).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, sequential FP64
- * transcription of the paper's time loop (Sec. 3, steps (i)-(xii), and
+ * transcription of the paper's time loop (Sec. 3, steps (i)-(xiv), and
  * Algorithm 1 "Time loop sketch").  It exists to check the GPU library
  * against.  Only the test-suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it; the product path never does.  It shares no

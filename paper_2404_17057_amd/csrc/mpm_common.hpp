@@ -34,7 +34,8 @@ enum Face { F_WALL = 0, F_INFLOW = 1, F_OUTFLOW = 2 };
 enum : uint8_t { NF_WALL_X = 1, NF_WALL_Y = 2, NF_WALL_Z = 4, NF_INFLOW = 8, NF_OBST = 16 };
 
 // Sticky error bits.
-enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_WALL = 8u, ERR_INTERNAL = 16u };
+// (A particle clamped back through a wall is counted, DG_WALL, not an error.)
+enum : uint32_t { ERR_NONPHYS = 1u, ERR_NONFINITE = 2u, ERR_OVERFLOW = 4u, ERR_INTERNAL = 16u };
 
 // Diagnostic counters (u64).
 enum { DG_MISMATCH = 0, DG_WALL = 1, DG_RECYCLE = 2 };   // diag[3] is reserved (0)

@@ -21,8 +21,8 @@
 //   k_update       S3: conditions on p2 on the tile load, G2PD, energy /
 //                  density update, move, recycling, scatter into the new
 //                  sorted order; per-tile CFL maxima and FP64 sums
-//                  (Sec. 3 (vii)-(xi))
-//   k_finalize     one workgroup per problem: next dt, t, parity (xii)
+//                  (Sec. 3 (vii)-(x), (xii))
+//   k_finalize     one workgroup per problem: next dt, t, parity ((xiii)-(xiv))
 // Grid accumulators and particle arrays are double-buffered by step parity.
 // (An in-kernel "last workgroup" hand-off would need an agent-scope release
 // per workgroup, which on this GPU writes back the whole L2 of an XCD.)
@@ -1070,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_reduce(WorkTab wt) {
 
 // -------------------------------------------------------------- finalize --
 // Next time step from the per-tile maxima of the step just done (Sec. 2.2,
-// CFL; Sec. 3 (xi)-(xii)) and the time.  Thread 0 of one
+// CFL; Sec. 3 (xiii)-(xiv)) and the time.  Thread 0 of one
 // workgroup per problem holds the reduced partials.
 // Time-stepping state of a problem, read in one batch of loads.
 struct StepState {

@@ -463,6 +463,32 @@ def random_blob(dim=2, n=12, count=300, seed=DEFAULT_SEED, shape=B2, margin=3,
         gradv=rng.uniform(-0.5, 0.5, size=(dim * dim, count)))
 
 
+def linear_flow_box(A, gprev=None, n=12, rho=1.0, p=1.0) -> Problem:
+    """Uniform gas on a regular 2x2 lattice (offsets 1/4, 3/4 of each cell,
+    no jitter) moving with the linear velocity field v = A x; `gprev` (2x2)
+    is the stored velocity gradient of every particle (None: zero).  Walls on
+    all faces.  Used by closed-form checks of one step."""
+    pb = uniform_box(dim=2, n=n, jitter=0.0, rho=rho, p=p)
+    A = np.asarray(A, dtype=np.float64)
+    pb.v = A @ pb.x
+    if gprev is not None:
+        pb.gradv = np.repeat(np.asarray(gprev, np.float64).reshape(4, 1), pb.n_particles, axis=1)
+    pb.name = f"linear_flow_{n}"
+    return pb
+
+
+def wall_escape(n=8, s=0.3, speed=1.0) -> Problem:
+    """One pressureless particle at s cells from the x_lo wall, half-way up,
+    moving at -speed along x; walls on all faces.  A time step beyond the
+    CFL bound carries it through the wall."""
+    h = 1.0 / n
+    return Problem(
+        name=f"wall_escape_{n}", dim=2, n=(n, n, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 0.0),
+        faces=((WALL, WALL),) * 3, x=np.array([[s * h], [0.5 + 0.5 * h]]),
+        v=np.array([[-speed], [0.0]]), mass=np.array([h * h / 4]), rho=np.array([1.0]),
+        eint=np.array([0.0]), ids=np.arange(1, dtype=np.uint32))
+
+
 WORKLOADS = {
     "sod": sod,
     "cylinder": cylinder,

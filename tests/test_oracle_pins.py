@@ -289,6 +289,18 @@ def test_boundary_conditions_in_a_step():
     assert (un2[obst] >= -1e-15).all()
     # the conditions changed something: the raw map had inward momentum there
     assert ((p * nrm).sum(axis=0)[obst] < 0).any()
+    # the force takes the same projection (eq. normali2 acts on both): the
+    # raw pressure force of the gas around the obstacle pushes its nodes
+    # inwards, the conditioned force has no inward part left
+    fscale = np.abs(f).max()
+    unf = (f * nrm).sum(axis=0)
+    assert (unf[obst] < -1e-6 * fscale).sum() > 10
+    assert ((fbc * nrm).sum(axis=0)[obst] >= -1e-15 * fscale).all()
+    # and only the inward part is removed: a node whose raw force already
+    # points out of the obstacle keeps it
+    out = obst & (unf > 1e-6 * fscale)
+    if out.any():
+        assert np.allclose(fbc[:, out], f[:, out], rtol=0, atol=1e-15 * fscale)
 
 
 def test_total_mass_constant_with_recycling():
@@ -305,10 +317,23 @@ def test_total_mass_constant_with_recycling():
 
 def test_recycled_particle_position_follows_the_hash():
     """A particle about to leave through the outflow re-enters at
-    x - L with y drawn from splitmix64(seed ^ step<<32 ^ id)."""
+    x - L with y drawn from splitmix64(seed ^ step<<32 ^ id), and takes the
+    whole inflow state (Sec. 4.1, regenerated at the inflow boundary):
+    velocity u_in, density rho_in, internal energy p_in / ((gamma-1) rho_in),
+    the recycling mass and a zero velocity gradient.  Its own state before
+    the exit is made different from the inflow state in every field, so a
+    field the recycling forgets to reset keeps a visibly wrong value."""
     pb = W.cylinder(nx=32, ny=16, steps=1)
     k = int(np.argmax(pb.x[0]))            # right-most particle
     pb.x[0, k] = 1.0 - 1e-6
+    pb.mass = pb.mass.copy()
+    pb.mass[k] *= 1.7
+    pb.rho = pb.rho.copy()
+    pb.rho[k] = 2.0
+    pb.eint = pb.eint.copy()
+    pb.eint[k] *= 3.0
+    pb.gradv = np.zeros((4, pb.n_particles))
+    pb.gradv[:, k] = (0.4, -0.2, 0.3, -0.9)
     o = O.Oracle(pb)
     dt = o.status()["dt_next"]
     o.step(1)
@@ -319,6 +344,126 @@ def test_recycled_particle_position_follows_the_hash():
     assert 0 <= x[0, k] < dt * 4
     assert o.particles(O.F_RHO)[k] == 1.4
     assert np.array_equal(o.particles(O.F_V)[:, k], [3.0, 0.0])
+    assert o.particles(O.F_E)[k] == pytest.approx(1.0 / (0.4 * 1.4), rel=1e-15)
+    assert o.particles(O.F_M)[k] == pb.recycle_mass
+    assert np.array_equal(o.particles(O.F_G)[:, k], np.zeros(4))
+    assert o.particles(O.F_Q)[k] == 0.0
+    # a particle that stays inside keeps its own, updated state
+    j = int(np.argmin(pb.x[0]))
+    assert o.particles(O.F_M)[j] == pb.mass[j]
+
+
+# ------------------------------------------------ closed-form single steps --
+
+def _deep_interior(pb):
+    """Particles in cells 2 .. n-3 on both axes: every node of their stencil
+    is an interior B2 node with a full lattice support.  The lattice is
+    symmetric about such a node's Greville point, so the P2G of a linear
+    field divided by the nodal mass is that field at the node, and the P2GD
+    of a uniform (P+Q) Vol is zero there."""
+    c = np.floor((pb.x[:2] - np.array(pb.lo[:2])[:, None]) / pb.h).astype(int)
+    n = np.array(pb.n[:2])[:, None]
+    return ((c >= 2) & (c <= n - 3)).all(axis=0)
+
+
+@pytest.mark.parametrize("case", ["compression", "expansion_after_compression"])
+def test_linear_flow_step_closed_form(case):
+    """One step of the uniform linear flow v = A x (Sec. 3 steps (ii)-(ix)),
+    closed form for deep-interior particles:
+      Vbar = A X, V' = V (no interior force), G' = A,
+      rho' = rho / (1 + dt tr A)                         (step (viii)),
+      e'   = e - dt (P + Q) tr A / rho  with the OLD rho (step (viii)),
+    where Q is the artificial pressure of the lagged divergence tr G of the
+    previous step (reading: the same Q in the force of (ii) and the energy
+    of (viii)).  Case 1 starts from G = 0 under compression (tr A < 0): the
+    lagged Q is 0 while the current divergence would give Q > 0.  Case 2
+    starts from a compressive stored G (tr G < 0) under expansion
+    (tr A > 0): the lagged Q > 0 while the current divergence gives 0.  An
+    update that divides by the new density, or takes Q from the current
+    divergence, misses these values by far more than rounding."""
+    if case == "compression":
+        A = np.array([[-0.8, 0.3], [0.5, -0.4]])
+        gprev = None
+    else:
+        A = np.array([[0.7, -0.2], [0.6, 0.5]])
+        gprev = [[-2.0, 0.1], [0.3, -1.0]]
+    pb = W.linear_flow_box(A, gprev)
+    dt = 1e-3
+    o = O.Oracle(pb)
+    o.set_dt(dt)
+    assert o.step(1) == 0
+    sel = _deep_interior(pb)
+    assert sel.sum() >= 100
+    trA = np.trace(A)
+    rho0, e0 = pb.rho[sel], pb.eint[sel]
+    P0 = 0.4 * rho0 * e0
+    c0 = np.sqrt(1.4 * P0 / rho0)
+    dprev = 0.0 if gprev is None else float(np.trace(np.asarray(gprev)))
+    Q = np.array([O.artificial_viscosity(W.AV_PAPER, 1.0, 1.0, 1.4, pb.h, r, p, dprev)
+                  for r, p in zip(rho0, P0)])
+    if case == "compression":
+        assert (Q == 0).all()
+        # what the current divergence would have given: clearly not zero
+        assert O.artificial_viscosity(W.AV_PAPER, 1.0, 1.0, 1.4, pb.h, 1.0, P0[0], trA) > 0.05
+    else:
+        assert (Q > 0.1).all()
+        assert np.allclose(Q, (pb.h * dprev) ** 2 - pb.h * c0 * dprev, rtol=1e-14)
+    vbar = o.particles(O.F_VBAR)[:, sel]
+    x0 = pb.x[:, sel]
+    assert np.abs(vbar - A @ x0).max() < 1e-13
+    assert np.abs(o.particles(O.F_V)[:, sel] - pb.v[:, sel]).max() < 1e-12
+    G = o.particles(O.F_G)[:, sel]
+    assert np.abs(G - A.reshape(4, 1)).max() < 1e-11
+    rho1 = o.particles(O.F_RHO)[sel]
+    e1 = o.particles(O.F_E)[sel]
+    assert np.allclose(rho1, rho0 / (1.0 + dt * trA), rtol=1e-13, atol=0)
+    assert np.allclose(e1, e0 - dt * (P0 + Q) * trA / rho0, rtol=1e-13, atol=0)
+    # the move uses Vbar: X' = X + dt A X
+    assert np.abs(o.particles(O.F_X)[:, sel] - (x0 + dt * (A @ x0))).max() < 1e-15
+
+
+def test_cfl_takes_the_g2p_velocity():
+    """The next time step bounds both particle velocities of the step, |V'|
+    and the G2P velocity |Vbar| of the move (Sec. 3 (xiii): momentum over mass
+    and Vbar; reading of the CFL velocity set).  Gas at rest next to an
+    inflow face with u_in = 4: the inflow nodes carry m u_in, so the first
+    cell's particles move with |Vbar| ~ 2, while V' stays small (inflow
+    nodes carry no force).  dt_next is then CFL h / (max|Vbar| + c_max)."""
+    pb = W.uniform_box(dim=2, n=12, jitter=0.0, rho=1.0, p=1.0)
+    pb.faces = ((W.INFLOW, W.WALL), (W.WALL, W.WALL), (W.WALL, W.WALL))
+    pb.inflow_rho, pb.inflow_p, pb.inflow_u = 1.0, 1.0, (4.0, 0.0, 0.0)
+    o = O.Oracle(pb)
+    o.set_dt(1e-3)
+    assert o.step(1) == 0
+    vb = np.sqrt((o.particles(O.F_VBAR) ** 2).sum(axis=0)).max()
+    v1 = np.sqrt((o.particles(O.F_V) ** 2).sum(axis=0)).max()
+    assert vb > 1.5 and vb > 5 * v1
+    rho = o.particles(O.F_RHO)
+    c = np.sqrt(np.maximum(1.4 * o.particles(O.F_P) / rho, 0.0)).max()
+    assert o.status()["dt_next"] == pytest.approx(0.3 * pb.h / (vb + c), rel=1e-14)
+
+
+def test_wall_escape_is_clamped_and_counted():
+    """A particle pushed through a wall by a time step beyond the CFL bound
+    is put back on the wall and counted (Sec. 3 (ix); any exit other than
+    the outflow's recycling is clamped).  One pressureless particle at
+    s = 0.3 cells from the x_lo wall moving at -1: the wall node's normal
+    momentum is zeroed, so Vbar_x = -(1 - B0(s)) = -(1 - (1-s)^2) = -0.51,
+    and D = -1.4/h keeps J = 1 + dt D > 0 for dt = 0.65 h, while
+    X' = (0.3 - 0.65 * 0.51) h < 0."""
+    pb = W.wall_escape(n=8, s=0.3)
+    h = pb.h
+    o = O.Oracle(pb)
+    o.set_dt(0.65 * h)
+    assert o.step(1) == 0
+    vbar = o.particles(O.F_VBAR)
+    assert vbar[0, 0] == pytest.approx(-0.51, rel=1e-13)
+    assert o.particles(O.F_G)[0, 0] == pytest.approx(-1.4 / h, rel=1e-13)
+    x = o.particles(O.F_X)
+    assert x[0, 0] == 0.0
+    assert x[1, 0] == pytest.approx(4.5 * h, abs=1e-15)
+    assert o.status()["wall_escapes"] == 1
+    assert o.particles(O.F_RHO)[0] == pytest.approx(1.0 / (1.0 - 0.65 * 1.4), rel=1e-13)
 
 
 # ------------------------------------------------------------------- Sod --
