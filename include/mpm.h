@@ -63,7 +63,8 @@ enum {
     MPM_E_NONPHYSICAL = -4,  /* J <= 0 or a non-finite value on the device     */
     MPM_E_OVERFLOW = -5,     /* fixed-point accumulator out of range           */
     MPM_E_UNSUPPORTED = -6,  /* valid request this build does not implement    */
-    MPM_E_STATE = -7         /* operation not allowed in the handle's state    */
+    MPM_E_STATE = -7,        /* operation not allowed in the handle's state    */
+    MPM_E_SCRATCH = -8       /* request larger than the fixed scratch buffer   */
 };
 
 /* Basis functions (Sec. 2.2: Q1 bilinear/trilinear elements; quadratic
@@ -233,6 +234,19 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
 enum { MPM_G_M = 0, MPM_G_P = 1, MPM_G_F = 2, MPM_G_PUPD = 3, MPM_G_P2 = 4,
        MPM_G_FBC = 5, MPM_G_FLAGS = 6 };
 int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid it): mpm_read_grid with the
+ * same arguments and output, staged through a fixed device buffer of the
+ * library (32 MiB per GPU, held until the process ends) instead of a
+ * temporary allocation; it calls no allocating routine.  A snapshot larger
+ * than the buffer (ncomp * nodes * 8 bytes > 32 MiB, e.g. a 2D grid of
+ * more than 2^21 nodes for a vector field) returns MPM_E_SCRATCH.  Every
+ * call on a GPU uses that GPU's one buffer: calls that overlap on one GPU
+ * (different host threads, or streams not ordered with each other) race
+ * and must not be made.  Synchronises the stream.  Errors: MPM_E_ARG,
+ * MPM_E_SCRATCH, MPM_E_HIP. */
+int mpm_read_grid_noalloc(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);
 
 /* Sec. 3 (xiii)-(xiv) (the time step and the time it advances to) and the
  * checks of a run: time, next and last time step, completed steps and FP64

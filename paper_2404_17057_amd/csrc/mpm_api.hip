@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mpm.h"
@@ -35,6 +36,30 @@ constexpr int graph_steps(int level) { return kGraphSteps >> level; }
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Fixed device scratch of mpm_read_grid_noalloc: the staging buffer of one
+// grid snapshot.  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address, per device, comes from hipGetSymbolAddress (scratch_address).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices];
+
+// Device address of the current device's `scratch`, resolved once per device.
+int scratch_address(double **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MPM_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MPM_E_HIP;
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return MPM_OK;
+}
 
 struct Layout {
     int dim, shape, prec;
@@ -188,6 +213,7 @@ struct mpm_handle {
     ProbDev *dev;          // device descriptor (workspace start)
     char *ws;
     int reported_err;
+    double *scratch;       // this device's copy of `scratch` (mpm_read_grid_noalloc)
     // graphs of single-problem stepping, captured by the first mpm_step
     hipGraphExec_t gexec[kGraphLevels];
     hipStream_t cap;
@@ -245,6 +271,7 @@ const char *mpm_strerror(int code) {
     case MPM_E_OVERFLOW: return "fixed-point accumulator overflow";
     case MPM_E_UNSUPPORTED: return "unsupported configuration";
     case MPM_E_STATE: return "handle is in an error state";
+    case MPM_E_SCRATCH: return "request larger than the fixed device scratch buffer (32 MiB)";
     default: return "unknown status";
     }
 }
@@ -302,6 +329,7 @@ int mpm_init(const mpm_desc *d, const mpm_particles_host *pp, const mpm_obstacle
 
     mpm_handle *H = (mpm_handle *)calloc(1, sizeof(mpm_handle));
     if (!H) return MPM_E_ARG;
+    if (scratch_address(&H->scratch) != MPM_OK) { free(H); return MPM_E_HIP; }
     H->L = L;
     H->ws = (char *)dev_workspace;
     H->dev = (ProbDev *)(H->ws + L.off_prob);
@@ -667,6 +695,22 @@ int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stre
     if (!st) st = hip_ok(hipStreamSynchronize(s));
     if (!st) st = hip_ok(hipMemcpy(host_out, tmp, bytes, hipMemcpyDeviceToHost));
     (void)hipFree(tmp);
+    return st;
+}
+
+int mpm_read_grid_noalloc(mpm_handle *h, int32_t which, double *host_out, void *hip_stream) {
+    if (!h || !host_out || which < MPM_G_M || which > MPM_G_FLAGS) return MPM_E_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int ncomp = (which == MPM_G_M || which == MPM_G_FLAGS) ? 1 : h->L.dim;
+    const size_t bytes = (size_t)ncomp * h->L.nnodes * 8;
+    if (bytes > kScratchBytes) return MPM_E_SCRATCH;
+    if (!h->scratch) return MPM_E_STATE;
+    // the kernel writes every element of the snapshot: nothing of the last
+    // call's contents is read
+    launch_grid_diag(h->L.dim, h->L.shape, h->L.prec, h->dev, h->host, which, h->scratch, s);
+    int st = hip_ok(hipGetLastError());
+    if (!st) st = hip_ok(hipMemcpyAsync(host_out, h->scratch, bytes, hipMemcpyDeviceToHost, s));
+    if (!st) st = hip_ok(hipStreamSynchronize(s));
     return st;
 }
 

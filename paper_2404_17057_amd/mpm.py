@@ -16,8 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm.so")
 
-OK, E_ARG, E_WORKSPACE, E_HIP, E_NONPHYSICAL, E_OVERFLOW, E_UNSUPPORTED, E_STATE = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+OK, E_ARG, E_WORKSPACE, E_HIP, E_NONPHYSICAL, E_OVERFLOW, E_UNSUPPORTED, E_STATE, E_SCRATCH = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
 Q1, B2 = 1, 2
 FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64 = 0, 1, 2, 3
 PRECISION_NAMES = {FP64: "fp64", FP32_ACC_F64: "fp32_acc_f64",
@@ -26,7 +26,7 @@ F_X, F_V, F_M, F_RHO, F_E, F_P, F_Q, F_G, F_VOL, F_ID = range(10)
 G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS = range(7)
 
 EXPORTS = ["mpm_footprint", "mpm_init", "mpm_step", "mpm_step_batch", "mpm_read_fields",
-           "mpm_read_grid", "mpm_status", "mpm_counters", "mpm_profile_step", "mpm_grid_shape",
+           "mpm_read_grid", "mpm_read_grid_noalloc", "mpm_status", "mpm_counters", "mpm_profile_step", "mpm_grid_shape",
            "mpm_destroy", "mpm_strerror"]
 SWEEPS = ["p2g", "frame_reduce", "g2p_p2g", "tilescan", "cellscan", "update", "finalize"]
 
@@ -86,6 +86,7 @@ def lib():
         L.mpm_step_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_int64), vp]
         L.mpm_read_fields.argtypes = [vp, C.c_uint32, C.POINTER(_DP), vp]
         L.mpm_read_grid.argtypes = [vp, C.c_int32, _DP, vp]
+        L.mpm_read_grid_noalloc.argtypes = [vp, C.c_int32, _DP, vp]
         L.mpm_status.argtypes = [vp, _DP, _DP, _DP, C.POINTER(C.c_int64), _DP, vp]
         L.mpm_counters.argtypes = [vp, C.POINTER(C.c_uint64), vp]
         L.mpm_profile_step.argtypes = [vp, C.c_int64, _DP, vp]
@@ -245,6 +246,16 @@ class Simulation:
         rc = lib().mpm_read_grid(self._h, which, out.ctypes.data_as(_DP), self._sp())
         if rc:
             raise MPMError(rc, "mpm_read_grid")
+        return out if nc > 1 else out[0]
+
+    def grid_noalloc(self, which: int) -> np.ndarray:
+        """The grid snapshot of `grid`, through the entry point that allocates
+        no device memory (fixed 32 MiB scratch per GPU)."""
+        nc = 1 if which in (G_M, G_FLAGS) else self.dim
+        out = np.empty((nc, self.nnodes))
+        rc = lib().mpm_read_grid_noalloc(self._h, which, out.ctypes.data_as(_DP), self._sp())
+        if rc:
+            raise MPMError(rc, "mpm_read_grid_noalloc")
         return out if nc > 1 else out[0]
 
     def status(self) -> dict:
