@@ -378,8 +378,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--nx", type=int, default=1024)
-    ap.add_argument("--serve-requests", type=int, default=100,
+    ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving stream (Poisson, 200/s, seed 2404; 0 = skip)")
+    ap.add_argument("--serve-sustained-requests", type=int, default=300,
+                    help="requests of the second serving run, offered at 70 %% of the measured capacity")
     ap.add_argument("--no-serve-sustained", action="store_true",
                     help="skip the second serving run at 70 %% of the measured capacity")
     ap.add_argument("--ablation", action="store_true",
@@ -543,24 +545,34 @@ def main():
         from paper_2404_17057_amd import serving as S
         specs = W.request_stream(n=args.serve_requests, rate=200.0, seed=2404)
         cache = W.LatticeCache()
+        prog = lambda k: log(f"serving: {k} requests done")
         srv = S.Server(S.GPUBackend(G.FP32_FIX64), lambda sp: W.build_request(sp, cache),
-                       hbm_budget=64 << 30, max_slots=64, steps_per_launch=16)
+                       hbm_budget=64 << 30, max_slots=64, steps_per_launch=16, progress=prog)
         done = srv.run(specs)
         serving = S.summarize(done)
         serving.update({"stream": f"{args.serve_requests} requests, Poisson 200/s, seed 2404",
                         "precision": "fp32 state, int64 fixed-point P2G", "max_slots": 64,
-                        "steps_per_launch": 16})
+                        "steps_per_launch": 16, "max_batch": max(srv.batch_sizes),
+                        "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
+                        "batched_launches": len(srv.batch_sizes),
+                        "admissions_during_a_batch": srv.overlapped_admissions,
+                        "failed": [dict(req_id=d.req_id, status=d.status, family=specs[d.req_id].family,
+                                        nx=specs[d.req_id].nx, ny=specs[d.req_id].ny, steps=d.steps,
+                                        seed=specs[d.req_id].seed, mach=specs[d.req_id].mach)
+                                   for d in done if d.status != 0]})
         log(f"serving: {serving}")
         if not args.no_serve_sustained:
             # The same request mix at a rate the device sustains: 70 % of the
             # throughput just measured, divided by the mean work per request.
             mean_work = float(np.mean([d.particles * d.steps for d in done]))
             rate = 0.7 * serving["aggregate_particle_steps_per_s"] / mean_work
-            specs = W.request_stream(n=args.serve_requests, rate=rate, seed=2404)
+            specs = W.request_stream(n=args.serve_sustained_requests, rate=rate, seed=2404)
             srv = S.Server(S.GPUBackend(G.FP32_FIX64), lambda sp: W.build_request(sp, cache),
-                           hbm_budget=64 << 30, max_slots=64, steps_per_launch=16)
+                           hbm_budget=64 << 30, max_slots=64, steps_per_launch=16, progress=prog)
             sus = S.summarize(srv.run(specs))
-            sus.update({"stream": f"{args.serve_requests} requests, Poisson {rate:.2f}/s, seed 2404",
+            sus.update({"stream": f"{args.serve_sustained_requests} requests, Poisson {rate:.2f}/s, seed 2404",
+                        "max_batch": max(srv.batch_sizes),
+                        "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
                         "offered_utilisation": 0.7,
                         "offered_particle_steps_per_s": rate * mean_work})
             serving["sustained"] = sus

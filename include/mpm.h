@@ -29,9 +29,9 @@
  *   - Device memory: the caller owns one device workspace of at least
  *     mpm_footprint() bytes per problem and keeps it alive until
  *     mpm_destroy().  The library allocates no device memory on the stepping
- *     path; mpm_read_grid allocates a temporary buffer (mpm_read_grid_noalloc
- *     does not), and mpm_step_batch keeps one small device table of its
- *     captured graphs per process and device.
+ *     path beyond what the HIP runtime takes to instantiate the captured
+ *     step graphs; mpm_read_grid allocates a temporary buffer
+ *     (mpm_read_grid_noalloc does not).
  *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL = the
  *     default stream).  All work is enqueued on it; mpm_step and
  *     mpm_step_batch return without waiting.
@@ -190,8 +190,13 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream);
  * launch whose workgroups cover the tiles of all problems.  Problems must
  * share dim, shape and precision (else MPM_E_UNSUPPORTED).  n_steps[i]
  * steps for problem i (>= 0); problems that finish early idle.  Up to 64
- * problems per call.  Asynchronous.  Errors: MPM_E_ARG, MPM_E_UNSUPPORTED,
- * MPM_E_STATE, MPM_E_HIP. */
+ * problems per call.  The steps are replays of captured graphs (16, 8, 4, 2
+ * and 1 steps): the library keeps, per device, the graphs of the last batch
+ * composition (the set of problems), and a call with another composition
+ * captures its graphs again (a few milliseconds of host work, before
+ * anything is enqueued).  Asynchronous; calls from several host threads are
+ * serialised.  Errors: MPM_E_ARG (also a negative step count),
+ * MPM_E_UNSUPPORTED, MPM_E_STATE, MPM_E_HIP. */
 int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps,
                    void *hip_stream);
 
@@ -224,15 +229,21 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
                     void *hip_stream);
 
 /* Grid snapshot of the last completed step as double, node grid x fastest,
- * component-major (dim comps except MPM_G_M and MPM_G_FLAGS):
- * raw P2G mass / momentum / force, momentum after the conditions and the
- * update, force after the conditions, re-mapped momentum after the
- * conditions, and the node flags.  2D grids hold each node's finished sum
- * in the state precision (the value the gather sweeps use); 3D grids hold
- * the accumulator words (exact in the fixed-point mode).  Allocates a
- * temporary device buffer.  Synchronises the stream. */
+ * component-major (dim comps for MPM_G_P .. MPM_G_FBC, one otherwise):
+ * raw P2G mass / momentum / force (Sec. 3 (ii)), momentum after the
+ * conditions and the update ((iii)-(iv)), force after the conditions,
+ * re-mapped momentum after the conditions ((vi)-(vii)), and the node flags.
+ * 2D grids hold each node's finished sum in the state precision (the value
+ * the gather sweeps use); 3D grids hold the accumulator words (exact in the
+ * fixed-point mode).
+ * MPM_G_MPROJ and MPM_G_VOLPROJ are not part of a step: the P2G (eq.
+ * p2g_gen) of the particle masses and of the volumes M / rho at the current
+ * positions, computed when asked with FP64 atomics; their ratio where the
+ * volume is positive is the grid-projected density, an Eulerian read-out
+ * of the particle density.  Allocates a temporary device buffer.
+ * Synchronises the stream.  Errors: MPM_E_ARG, MPM_E_HIP. */
 enum { MPM_G_M = 0, MPM_G_P = 1, MPM_G_F = 2, MPM_G_PUPD = 3, MPM_G_P2 = 4,
-       MPM_G_FBC = 5, MPM_G_FLAGS = 6 };
+       MPM_G_FBC = 5, MPM_G_FLAGS = 6, MPM_G_MPROJ = 7, MPM_G_VOLPROJ = 8 };
 int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream);
 
 /* For callers that cannot allocate device memory (code under graph capture,

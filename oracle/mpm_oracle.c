@@ -463,7 +463,9 @@ static double ratio(double u, double m) { return m > 0.0 ? u / m : 0.0; }
 
 /* The P2G sums of particles k0 .. k1-1, in id order, added into out:
  * which = 0: mass, momentum and internal force (step (ii)), out = m, p[3],
- * f[3]; which = 1: the updated momentum M V' (step (vi)), out = p2[3]. */
+ * f[3]; which = 1: the updated momentum M V' (step (vi)), out = p2[3];
+ * which = 2: mass and volume M / rho at the current positions (the
+ * grid-projected density read-out, not a step), out = m, vol. */
 static void scatter_range(const orc_state *s, int which, int64_t k0, int64_t k1, double *const *out) {
     const orc_problem *pb = &s->pb;
     const int dim = pb->dim;
@@ -476,6 +478,13 @@ static void scatter_range(const orc_state *s, int which, int64_t k0, int64_t k1,
             for (int c = 0; c < st.count; ++c)
                 for (int a = 0; a < dim; ++a)
                     out[a][st.node[c]] += s->M[k] * s->v[a][k] * st.w[c];
+            continue;
+        }
+        if (which == 2) {
+            for (int c = 0; c < st.count; ++c) {
+                out[0][st.node[c]] += s->M[k] * st.w[c];
+                out[1][st.node[c]] += s->M[k] / s->rho[k] * st.w[c];
+            }
             continue;
         }
         double P = eos_pressure(gam, s->rho[k], s->E[k]);
@@ -498,7 +507,7 @@ static void scatter_range(const orc_state *s, int which, int64_t k0, int64_t k1,
  * order. */
 static void scatter(orc_state *s, int which, double *const *out) {
     const int dim = s->pb.dim;
-    const int nq = which == 0 ? 1 + 2 * dim : dim;
+    const int nq = which == 0 ? 1 + 2 * dim : (which == 1 ? dim : 2);
     const int64_t NN = s->nnodes;
     if (s->nthreads <= 1) {
         scatter_range(s, which, 0, s->np, out);
@@ -747,6 +756,19 @@ int orc_get_grid(const orc_state *s, int which, double *out) {
     default: return ORC_E_ARG;
     }
     for (int a = 0; a < dim; ++a) memcpy(out + a * NN, src[a], NN * sizeof(double));
+    return ORC_OK;
+}
+
+int orc_projected(orc_state *s, double *mass, double *vol) {
+    /* P2G of the particle masses and volumes M / rho at the current
+     * positions: the grid-projected density is mass / vol where vol > 0
+     * (an Eulerian read-out of the particle density; eq. p2g_gen with the
+     * mass and the volume as particle fields). */
+    if (!s || !mass || !vol) return ORC_E_ARG;
+    memset(mass, 0, (size_t)s->nnodes * sizeof(double));
+    memset(vol, 0, (size_t)s->nnodes * sizeof(double));
+    double *out[2] = {mass, vol};
+    scatter(s, 2, out);
     return ORC_OK;
 }
 

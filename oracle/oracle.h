@@ -85,6 +85,12 @@ int orc_set_dt(orc_state *s, double dt);
  * n > 1 in a build without OpenMP. */
 int orc_set_threads(orc_state *s, int n);
 
+/* Read-out of the grid-projected density: mass[i] = sum_k M_k phi_i(X_k)
+ * and vol[i] = sum_k (M_k / rho_k) phi_i(X_k) at the current positions (two
+ * arrays over the node grid, x fastest); the projected density is
+ * mass / vol where vol > 0. */
+int orc_projected(orc_state *s, double *mass, double *vol);
+
 /* Particle fields in id order, one double array of np per component. */
 #define ORC_F_X    0   /* dim components */
 #define ORC_F_V    1   /* dim */

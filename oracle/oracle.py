@@ -68,6 +68,7 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_set_dt.argtypes = [C.c_void_p, C.c_double]
         L.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
+        L.orc_projected.argtypes = [C.c_void_p, dp, dp]
         L.orc_get_particles.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_get_grid.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_grid_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
@@ -204,6 +205,16 @@ class Oracle:
         if rc:
             raise OracleError(rc, "orc_get_grid")
         return out if nc > 1 else out[0]
+
+    def projected(self):
+        """P2G of the masses and of the volumes M / rho at the current
+        positions: (mass, vol) over the nodes; density = mass / vol."""
+        m = np.empty(self.nnodes)
+        v = np.empty(self.nnodes)
+        rc = lib().orc_projected(self._h, _dptr(m), _dptr(v))
+        if rc:
+            raise OracleError(rc, "orc_projected")
+        return m, v
 
     def status(self) -> dict:
         t, dtn, dtl = C.c_double(), C.c_double(), C.c_double()

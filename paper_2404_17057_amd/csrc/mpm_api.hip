@@ -237,12 +237,51 @@ void make_tables(mpm_handle *const *hs, int n, WorkTab &tiles, WorkTab &single) 
     tiles.max_tiles = single.max_tiles = mt;
 }
 
-void enqueue_steps(mpm_handle *const *hs, int n, int steps, hipStream_t s) {
-    WorkTab tiles, single;
-    make_tables(hs, n, tiles, single);
-    const Layout &L = hs[0]->L;
-    for (int k = 0; k < steps; ++k) launch_step(L.dim, L.shape, L.prec, tiles, single, s);
+
+// Capture `steps` steps of the work tables into *exec: the executable graph
+// is updated in place when it exists (same topology, new kernel arguments),
+// else instantiated.
+int capture_steps(int dim, int shape, int prec, const WorkTab &tiles, const WorkTab &single, int steps,
+                  hipStream_t cap, hipGraphExec_t *exec) {
+    hipGraph_t g;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_E_HIP;
+    for (int k = 0; k < steps; ++k) launch_step(dim, shape, prec, tiles, single, cap);
+    if (hipStreamEndCapture(cap, &g) != hipSuccess) return MPM_E_HIP;
+    int st = MPM_OK;
+    if (*exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(*exec, g, &bad, &res) != hipSuccess || res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(*exec);
+            *exec = nullptr;
+        }
+    }
+    if (!*exec && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        *exec = nullptr;
+        st = MPM_E_HIP;
+    }
+    (void)hipGraphDestroy(g);
+    return st;
 }
+
+// Graphs of batched stepping, per device: the step graphs (16, 8, 4, 2, 1
+// steps) of the last batch composition seen at each level.  A composition
+// is the kernel variant and the work tables (the problems' descriptors and
+// tile counts): everything a captured launch bakes in, as the kernels read
+// the rest from the descriptors at run time.
+struct BatchKey {
+    int dim, shape, prec, pad;
+    WorkTab tiles;
+};
+struct BatchGraphs {
+    BatchKey key[kGraphLevels];
+    bool valid[kGraphLevels];
+    hipGraphExec_t exec[kGraphLevels];
+    hipStream_t cap;
+};
+std::mutex g_batch_mu;
+BatchGraphs g_batch[kMaxDevices];
 
 int read_dynamic(mpm_handle *h, ProbDev *out, hipStream_t s) {
     if (hipStreamSynchronize(s) != hipSuccess) return MPM_E_HIP;
@@ -508,7 +547,7 @@ int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps, voi
     if (!hs || n <= 0 || n > kMaxBatch || !n_steps) return MPM_E_ARG;
     long long maxn = 0;
     for (int i = 0; i < n; ++i) {
-        if (!hs[i]) return MPM_E_ARG;
+        if (!hs[i] || n_steps[i] < 0) return MPM_E_ARG;
         if (hs[i]->reported_err) return MPM_E_STATE;
         if (hs[i]->L.dim != hs[0]->L.dim || hs[i]->L.shape != hs[0]->L.shape ||
             hs[i]->L.prec != hs[0]->L.prec)
@@ -518,14 +557,42 @@ int mpm_step_batch(mpm_handle *const *hs, int32_t n, const int64_t *n_steps, voi
         maxn = std::max<long long>(maxn, n_steps[i]);
     }
     hipStream_t s = (hipStream_t)hip_stream;
-    WorkTab tiles, single;
-    make_tables(hs, n, tiles, single);
+    BatchKey key{};
+    key.dim = hs[0]->L.dim;
+    key.shape = hs[0]->L.shape;
+    key.prec = hs[0]->L.prec;
+    WorkTab single;
+    make_tables(hs, n, key.tiles, single);
     std::vector<long long> nn(n);
     for (int i = 0; i < n; ++i) nn[i] = n_steps[i];
     launch_arm(single, nn.data(), s);
-    for (long long k = 0; k < maxn; ++k)
-        launch_step(hs[0]->L.dim, hs[0]->L.shape, hs[0]->L.prec, tiles, single, s);
-    return hip_ok(hipGetLastError());
+    if (maxn == 0) return hip_ok(hipGetLastError());
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MPM_E_HIP;
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    BatchGraphs &B = g_batch[dev];
+    if (!B.cap && hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking) != hipSuccess) return MPM_E_HIP;
+    // Replays of the step graphs of this composition (16 steps, then the
+    // binary digits of the remainder), captured when the composition differs
+    // from the last one seen at that level.
+    auto level = [&](int lv) -> int {
+        if (!B.valid[lv] || memcmp(&B.key[lv], &key, sizeof(BatchKey)) != 0) {
+            B.valid[lv] = false;
+            const int st = capture_steps(key.dim, key.shape, key.prec, key.tiles, single, graph_steps(lv),
+                                         B.cap, &B.exec[lv]);
+            if (st) return st;
+            B.key[lv] = key;
+            B.valid[lv] = true;
+        }
+        return hip_ok(hipGraphLaunch(B.exec[lv], s));
+    };
+    long long left = maxn;
+    for (; left >= kGraphSteps; left -= kGraphSteps)
+        if (int st = level(0)) return st;
+    for (int lv = 1; lv < kGraphLevels; ++lv)
+        if (left & graph_steps(lv))
+            if (int st = level(lv)) return st;
+    return MPM_OK;
 }
 
 int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
@@ -544,16 +611,12 @@ int mpm_step(mpm_handle *h, int64_t n_steps, void *hip_stream) {
     if (!h->gexec[0]) {
         if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) return MPM_E_HIP;
         for (int lv = 0; lv < kGraphLevels; ++lv) {
-            hipGraph_t g;
-            if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPM_E_HIP;
-            enqueue_steps(one, 1, graph_steps(lv), h->cap);
-            if (hipStreamEndCapture(h->cap, &g) != hipSuccess) return MPM_E_HIP;
-            const hipError_t e = hipGraphInstantiate(&h->gexec[lv], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                h->gexec[lv] = nullptr;
-                for (int j = 0; j < lv; ++j) { (void)hipGraphExecDestroy(h->gexec[j]); h->gexec[j] = nullptr; }
-                return MPM_E_HIP;
+            const int st = capture_steps(h->L.dim, h->L.shape, h->L.prec, tiles, single, graph_steps(lv), h->cap,
+                                         &h->gexec[lv]);
+            if (st) {
+                for (int j = 0; j < kGraphLevels; ++j)
+                    if (h->gexec[j]) { (void)hipGraphExecDestroy(h->gexec[j]); h->gexec[j] = nullptr; }
+                return st;
             }
         }
     }
@@ -684,9 +747,9 @@ int mpm_read_fields(mpm_handle *h, uint32_t field_mask, double *const *host_out,
 }
 
 int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stream) {
-    if (!h || !host_out || which < MPM_G_M || which > MPM_G_FLAGS) return MPM_E_ARG;
+    if (!h || !host_out || which < MPM_G_M || which > MPM_G_VOLPROJ) return MPM_E_ARG;
     hipStream_t s = (hipStream_t)hip_stream;
-    const int ncomp = (which == MPM_G_M || which == MPM_G_FLAGS) ? 1 : h->L.dim;
+    const int ncomp = (which == MPM_G_M || which >= MPM_G_FLAGS) ? 1 : h->L.dim;
     const size_t bytes = (size_t)ncomp * h->L.nnodes * 8;
     double *tmp = nullptr;
     if (hipMalloc(&tmp, bytes) != hipSuccess) return MPM_E_HIP;
@@ -699,9 +762,9 @@ int mpm_read_grid(mpm_handle *h, int32_t which, double *host_out, void *hip_stre
 }
 
 int mpm_read_grid_noalloc(mpm_handle *h, int32_t which, double *host_out, void *hip_stream) {
-    if (!h || !host_out || which < MPM_G_M || which > MPM_G_FLAGS) return MPM_E_ARG;
+    if (!h || !host_out || which < MPM_G_M || which > MPM_G_VOLPROJ) return MPM_E_ARG;
     hipStream_t s = (hipStream_t)hip_stream;
-    const int ncomp = (which == MPM_G_M || which == MPM_G_FLAGS) ? 1 : h->L.dim;
+    const int ncomp = (which == MPM_G_M || which >= MPM_G_FLAGS) ? 1 : h->L.dim;
     const size_t bytes = (size_t)ncomp * h->L.nnodes * 8;
     if (bytes > kScratchBytes) return MPM_E_SCRATCH;
     if (!h->scratch) return MPM_E_STATE;

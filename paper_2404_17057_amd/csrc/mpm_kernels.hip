@@ -1612,6 +1612,37 @@ __global__ __launch_bounds__(kBlock) void k_grid_diag(ProbDev *P, int which, dou
     }
 }
 
+// Read-out of the grid-projected density (not part of a step): P2G of the
+// particle masses (which 0) or volumes M / rho (which 1) at the current
+// positions, FP64 atomics into a zeroed node array.
+__global__ __launch_bounds__(kBlock) void k_fill(double *out, long long n, double v) {
+    const long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+template <int DIM, int SHAPE, int PREC>
+__global__ __launch_bounds__(kBlock) void k_project(const ProbDev *P, int which, double *out) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    const long long k = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= P->np) return;
+    const int par = P->parity;
+    R x[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) x[a] = ((const R *)P->part[par][PF_X + a])[k];
+    const R M = ((const R *)P->part[par][PF_M])[k];
+    const R rho = ((const R *)P->part[par][PF_RHO])[k];
+    const double f = which == 0 ? (double)M : (double)M / (double)rho;
+    Stencil<DIM, SHAPE, R> st;
+    make_stencil<DIM, SHAPE, R>(P, x, st);
+    for (int jz = 0; jz < (DIM == 3 ? G::W : 1); ++jz)
+        for (int jy = 0; jy < G::W; ++jy)
+            for (int jx = 0; jx < G::W; ++jx) {
+                double w = (double)st.w[0][jx] * (double)st.w[1][jy];
+                if (DIM == 3) w *= (double)st.w[2][jz];
+                atomicAdd(&out[node_index(P, st.c[0] + jx, st.c[1] + jy, DIM == 3 ? st.c[2] + jz : 0)], f * w);
+            }
+}
+
 // ------------------------------------------------------------- launchers --
 static inline dim3 grid1(int n) { return dim3((unsigned)n); }
 
@@ -1658,10 +1689,16 @@ void launch_init_t(ProbDev *dP, const ProbDev &h, hipStream_t s) {
     hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(kWideBlock), 0, s, dP);
 }
 
-template <int DIM, int PREC>
+template <int DIM, int SHAPE, int PREC>
 void launch_grid_diag_t(ProbDev *dP, const ProbDev &h, int which, double *out, hipStream_t s) {
     const unsigned nb = (unsigned)((h.nnodes + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_grid_diag<DIM, PREC>), dim3(nb), dim3(kBlock), 0, s, dP, which, out);
+    if (which < 7) {
+        hipLaunchKernelGGL((k_grid_diag<DIM, PREC>), dim3(nb), dim3(kBlock), 0, s, dP, which, out);
+        return;
+    }
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, s, out, h.nnodes, 0.0);
+    const unsigned npb = (unsigned)((h.np + kBlock - 1) / kBlock);
+    if (npb) hipLaunchKernelGGL((k_project<DIM, SHAPE, PREC>), dim3(npb), dim3(kBlock), 0, s, dP, which - 7, out);
 }
 
 // Runtime dispatch over the instantiated variants.
@@ -1715,7 +1752,7 @@ void launch_init(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, hi
 
 void launch_grid_diag(int dim, int shape, int prec, ProbDev *dP, const ProbDev &h, int which,
                       double *out, hipStream_t s) {
-#define CALL_DIAG(D, S, Pr) launch_grid_diag_t<D, Pr>(dP, h, which, out, s)
+#define CALL_DIAG(D, S, Pr) launch_grid_diag_t<D, S, Pr>(dP, h, which, out, s)
     MPM_DISPATCH(dim, shape, prec, CALL_DIAG);
 #undef CALL_DIAG
 }

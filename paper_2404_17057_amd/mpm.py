@@ -23,7 +23,7 @@ FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64 = 0, 1, 2, 3
 PRECISION_NAMES = {FP64: "fp64", FP32_ACC_F64: "fp32_acc_f64",
                    FP32_ACC_F32: "fp32_acc_f32", FP32_FIX64: "fp32_fix64"}
 F_X, F_V, F_M, F_RHO, F_E, F_P, F_Q, F_G, F_VOL, F_ID = range(10)
-G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS = range(7)
+G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS, G_MPROJ, G_VOLPROJ = range(9)
 
 EXPORTS = ["mpm_footprint", "mpm_init", "mpm_step", "mpm_step_batch", "mpm_read_fields",
            "mpm_read_grid", "mpm_read_grid_noalloc", "mpm_status", "mpm_counters", "mpm_profile_step", "mpm_grid_shape",
@@ -241,7 +241,7 @@ class Simulation:
         return self.read([f])[f]
 
     def grid(self, which: int) -> np.ndarray:
-        nc = 1 if which in (G_M, G_FLAGS) else self.dim
+        nc = 1 if which in (G_M, G_FLAGS, G_MPROJ, G_VOLPROJ) else self.dim
         out = np.empty((nc, self.nnodes))
         rc = lib().mpm_read_grid(self._h, which, out.ctypes.data_as(_DP), self._sp())
         if rc:
@@ -251,7 +251,7 @@ class Simulation:
     def grid_noalloc(self, which: int) -> np.ndarray:
         """The grid snapshot of `grid`, through the entry point that allocates
         no device memory (fixed 32 MiB scratch per GPU)."""
-        nc = 1 if which in (G_M, G_FLAGS) else self.dim
+        nc = 1 if which in (G_M, G_FLAGS, G_MPROJ, G_VOLPROJ) else self.dim
         out = np.empty((nc, self.nnodes))
         rc = lib().mpm_read_grid_noalloc(self._h, which, out.ctypes.data_as(_DP), self._sp())
         if rc:

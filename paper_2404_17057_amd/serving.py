@@ -4,12 +4,14 @@ Requests arrive over time (a Poisson stream), each an independent 2D problem
 of its own grid and particle count.  The loop keeps the admitted problems
 resident in device memory and advances all of them together: every sweep of
 a step is one launch whose workgroups cover the tiles of every resident
-problem (`mpm_step_batch`), `steps_per_launch` steps per call.  A request is
-admitted as soon as a slot and enough device memory (its `mpm_footprint`)
-are free; admission runs on the host while the previous batch runs on the
-device, and the new problem joins the next batch.  Finished problems are read
-back and their memory returned.  Time-to-solution is completion time minus
-arrival time.
+problem (`mpm_step_batch`, replays of captured step graphs),
+`steps_per_launch` steps per call.  A request is admitted as soon as a slot
+and enough device memory (its `mpm_footprint`) are free.  As soon as a batch
+completes the next one is launched; the host work between batches (reading
+back the problems that just finished, building and initialising new ones on
+a side stream) then overlaps with it, and new problems join the batch after
+it.  Finished problems are read back and their memory returned.
+Time-to-solution is completion time minus arrival time.
 
 The loop talks to a backend with five calls (footprint, create, step_batch,
 finish, sync), so its scheduling can be exercised without a GPU.
@@ -75,6 +77,8 @@ class GPUBackend:
             self._ev.synchronize()
 
     def finish(self, sim):
+        # on the side stream: overlaps with the batch in flight on the main one
+        sim.stream = self.side
         rho = sim.read([self.G.F_RHO], check=False)[self.G.F_RHO]
         st = sim.status()
         sim.close()
@@ -85,7 +89,8 @@ class GPUBackend:
 class Server:
     def __init__(self, backend, build: Callable, hbm_budget: int = 64 << 30, max_slots: int = 64,
                  steps_per_launch: int = 16, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 progress: Optional[Callable[[int], None]] = None, progress_every: int = 100):
         self.backend = backend
         self.build = build
         self.budget = hbm_budget
@@ -93,6 +98,8 @@ class Server:
         self.k = steps_per_launch
         self.clock = clock
         self.sleep = sleep
+        self.progress = progress
+        self.progress_every = progress_every
         self.log: List[str] = []
 
     def run(self, specs: Sequence) -> List[Completed]:
@@ -103,11 +110,42 @@ class Server:
         done: List[Completed] = []
         t0 = self.clock()
         in_flight = False
+        # what ran concurrently: problems per batched launch, and admissions
+        # made while a batch was on the device
+        self.batch_sizes: List[int] = []
+        self.overlapped_admissions = 0
         while pending or queue or active:
+            finished = []
+            if in_flight:
+                self.backend.sync()
+                in_flight = False
+                keep = []
+                for a in active:
+                    if a.get("ran"):
+                        a["left"] -= a.pop("ran")
+                    (finished if a["left"] <= 0 and "launched" in a else keep).append(a)
+                active = keep
+            # the next batch goes out first; the host work below overlaps it
+            if active:
+                counts = [min(self.k, a["left"]) for a in active]
+                for a, c in zip(active, counts):
+                    a["ran"] = c
+                    a["launched"] = True
+                self.backend.step_batch([a["sim"] for a in active], counts)
+                self.batch_sizes.append(len(active))
+                in_flight = True
+            now = self.clock() - t0
+            for a in finished:
+                digest, rc = self.backend.finish(a["sim"])
+                used -= a["bytes"]
+                done.append(Completed(a["spec"].req_id, a["spec"].arrival, a["admitted"], now,
+                                      a["particles"], a["spec"].steps, digest, rc))
+                if self.progress and len(done) % self.progress_every == 0:
+                    self.progress(len(done))
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            # admissions (host work overlaps the batch in flight)
+            # admissions: the new problems join the batch after the one in flight
             while queue and len(active) < self.max_slots:
                 spec = queue[0]
                 pb = self.build(spec)
@@ -119,35 +157,11 @@ class Server:
                 queue.popleft()
                 sim = self.backend.create(pb)
                 used += need
+                self.overlapped_admissions += int(in_flight)
                 active.append(dict(sim=sim, spec=spec, left=spec.steps, bytes=need,
                                    admitted=self.clock() - t0, particles=pb.n_particles))
-            if in_flight:
-                self.backend.sync()
-                in_flight = False
-                now = self.clock() - t0
-                keep = []
-                for a in active:
-                    if a.get("ran"):
-                        a["left"] -= a.pop("ran")
-                    if a["left"] <= 0 and "launched" in a:
-                        digest, rc = self.backend.finish(a["sim"])
-                        used -= a["bytes"]
-                        done.append(Completed(a["spec"].req_id, a["spec"].arrival, a["admitted"], now,
-                                              a["particles"], a["spec"].steps, digest, rc))
-                    else:
-                        keep.append(a)
-                active = keep
-                continue
-            if not active:
-                if pending:
-                    self.sleep(max(0.0, min(0.01, pending[0].arrival - (self.clock() - t0))))
-                continue
-            counts = [min(self.k, a["left"]) for a in active]
-            for a, c in zip(active, counts):
-                a["ran"] = c
-                a["launched"] = True
-            self.backend.step_batch([a["sim"] for a in active], counts)
-            in_flight = True
+            if not in_flight and not active and pending:
+                self.sleep(max(0.0, min(0.01, pending[0].arrival - (self.clock() - t0))))
         return done
 
 

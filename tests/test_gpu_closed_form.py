@@ -146,3 +146,28 @@ def test_negative_pressure_matches_oracle(prec, tol):
         ref = o.particles(of)
         assert np.abs(s.field(gf) - ref).max() <= tol * np.abs(ref).max(), gf
     assert (s.field(G.F_P) < 0).sum() > 0
+
+
+# FP32 positions carry a rounding of 2^-24 |x|, up to 2^-24 L/h of a cell
+# (L/h = 256 here); a B2 weight moves by at most twice that per rounding
+# (|N'| <= 2 per cell), and five steps chain five roundings of the position.
+_PROJ_FP32_TOL = 5 * 2 * 2.0 ** -24 * 256
+
+
+@pytest.mark.parametrize("prec,tol", [(G.FP64, 1e-9), (G.FP32_FIX64, _PROJ_FP32_TOL)])
+def test_projected_density_matches_oracle(prec, tol):
+    """The read-out of the grid-projected density (P2G of M and of M / rho
+    at the current positions) against the oracle's, after 5 steps of the
+    256x128 cylinder: per node, relative to the largest value."""
+    _gpu()
+    pb = W.cylinder(nx=256, ny=128, steps=5)
+    o = O.Oracle(pb)
+    assert o.step(5) == 0
+    print(f"projected density prec {prec}", flush=True)
+    s = G.Simulation(pb, prec)
+    s.step(5)
+    m_o, v_o = o.projected()
+    m, v = s.grid(G.G_MPROJ), s.grid(G.G_VOLPROJ)
+    assert np.abs(m - m_o).max() <= tol * m_o.max()
+    assert np.abs(v - v_o).max() <= tol * v_o.max()
+    assert np.array_equal(m > 0, m_o > 0)

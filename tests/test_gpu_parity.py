@@ -160,20 +160,50 @@ def test_3d_fix64_blast_matches_oracle_and_is_order_free():
 
 
 def test_graph_replay_equals_eager_steps():
+    """mpm_step replays captured graphs (16 + 16 + 2 + 1 steps); the
+    per-sweep profile launches every sweep of every step eagerly."""
     _gpu()
     pb = W.quadrant(n=64)
     a = G.Simulation(pb, G.FP32_FIX64)
     b = G.Simulation(pb, G.FP32_FIX64)
-    a.step(35)                     # two graph replays of 16 steps + 3 eager
-    for _ in range(35):
-        b.step(1)
-    # G: written whole only by the last step of each run (here step 35 of
-    # one run against every step of 35 runs); Q: from the stored tr G
+    a.step(35)
+    b.profile(35)
+    # G: written whole by the last step of each run (step 35 of one run
+    # in both); Q: from the stored tr G
     fs = [G.F_X, G.F_RHO, G.F_V, G.F_G, G.F_Q]
     ra, rb = a.read(fs), b.read(fs)
     for f in ra:
         assert np.array_equal(ra[f], rb[f]), f
     assert a.status()["step"] == b.status()["step"] == 35
+
+
+def test_batched_graphs_equal_eager_steps():
+    """mpm_step_batch replays the step graphs of the batch's composition and
+    captures them again when the composition changes (here: all three
+    problems, two of them, one alone, all three at another level, then a
+    replay of the first composition's cached graph).  Each problem ends bit
+    for bit where its eager run alone (sweep-by-sweep launches) ends."""
+    _gpu()
+    pbs = [W.sod(nx=128, ny=4, t_end=0.0), W.quadrant(n=32, seed=3), W.cylinder(nx=64, ny=32)]
+    fs = [G.F_X, G.F_V, G.F_RHO, G.F_E, G.F_G]
+    eager = []
+    for pb in pbs:
+        s = G.Simulation(pb, G.FP32_FIX64)
+        s.profile(43)
+        eager.append(s.read(fs))
+        s.close()
+    sims = [G.Simulation(pb, G.FP32_FIX64) for pb in pbs]
+    A, B, C = sims
+    G.step_batch(sims, [16, 16, 16])
+    G.step_batch([A, C], [5, 5])
+    G.step_batch([B], [11])
+    G.step_batch(sims, [6, 0, 6])
+    G.step_batch(sims, [16, 16, 16])
+    for s, ref in zip(sims, eager):
+        assert s.status()["step"] == 43
+        got = s.read(fs)
+        for f in fs:
+            assert np.array_equal(got[f], ref[f]), f
 
 
 def test_batched_step_equals_single_problem_steps():

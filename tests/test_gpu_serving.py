@@ -36,6 +36,10 @@ def test_served_results_equal_alone_runs():
     srv = S.Server(be, build, hbm_budget=1 << 30, max_slots=4, steps_per_launch=16)
     done = srv.run(specs)
     assert len(done) == len(specs) and all(d.status == 0 for d in done)
+    # the requests really shared launches, and some were admitted while a
+    # batch was on the device
+    assert max(srv.batch_sizes) > 1
+    assert srv.overlapped_admissions >= 1
     for d in done:
         spec = specs[d.req_id]
         sim = G.Simulation(build(spec), G.FP32_FIX64)
@@ -77,6 +81,8 @@ def test_failing_request_does_not_disturb_the_others():
     srv = S.Server(S.GPUBackend(G.FP32_FIX64), build, hbm_budget=1 << 30, max_slots=6, steps_per_launch=16)
     done = {d.req_id: d for d in srv.run(specs)}
     assert len(done) == len(specs)
+    assert max(srv.batch_sizes) > 1
+    assert srv.overlapped_admissions >= 1
     assert done[2].status == G.E_NONPHYSICAL
     for i, spec in enumerate(specs):
         if i == 2:

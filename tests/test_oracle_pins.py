@@ -353,6 +353,29 @@ def test_recycled_particle_position_follows_the_hash():
     assert o.particles(O.F_M)[j] == pb.mass[j]
 
 
+def test_projected_density_read_out():
+    """The grid-projected density sum M phi / sum (M / rho) phi is the
+    density itself wherever the gas has one density (whatever the masses and
+    positions), and its two sums carry the total mass and volume (partition
+    of unity).  Two regions of different density: each region's interior
+    nodes hold its own density, nodes straddling the interface lie between."""
+    pb = W.uniform_box(dim=2, n=12, jitter=0.05, rho=1.3, p=1.0)
+    pb.mass = pb.mass * np.random.default_rng(5).uniform(0.5, 1.5, pb.n_particles)
+    pb.rho = np.where(pb.x[0] < 0.5, 1.3, 0.4)
+    o = O.Oracle(pb)
+    m, v = o.projected()
+    assert m.sum() == pytest.approx(pb.mass.sum(), rel=1e-14)
+    assert v.sum() == pytest.approx((pb.mass / pb.rho).sum(), rel=1e-14)
+    nodes = pb.node_counts()
+    X = np.tile(pb.lo[0] + W.node_axis(pb.n[0], pb.shape) * pb.h, nodes[1])
+    rho = np.where(v > 0, m / np.where(v > 0, v, 1.0), np.nan)
+    left, right = X < 0.5 - 2 * pb.h, X > 0.5 + 2 * pb.h
+    assert np.allclose(rho[left], 1.3, rtol=1e-14)
+    assert np.allclose(rho[right], 0.4, rtol=1e-14)
+    mid = ~left & ~right
+    assert ((rho[mid] > 0.4 - 1e-14) & (rho[mid] < 1.3 + 1e-14)).all()
+
+
 # ------------------------------------------------ closed-form single steps --
 
 def _deep_interior(pb):
