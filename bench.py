@@ -279,7 +279,7 @@ def blast3d(args):
     from paper_2404_17057_amd import workloads as W
     pb = W.blast3d(n=args.blast_n, steps=args.blast_steps)
     log(f"blast3d {args.blast_n}^3: {pb.n_particles} particles")
-    r = time_gpu(pb, G.FP32_FIX64, args.blast_steps, args.blast_warmup, -1)
+    r = time_gpu(pb, G.FP32_FIX64, args.blast_steps, args.blast_warmup, args.blast_profile_steps)
     nt = [(args.blast_n + 7) // 8, (args.blast_n + 7) // 8, (args.blast_n + 3) // 4]
     b = sweep_bytes(pb, r["nodes"], nt[0] * nt[1] * nt[2] * 256, 4, 8)
     step_bytes = sum(b.values())
@@ -391,6 +391,10 @@ def main():
     ap.add_argument("--ablation-oracle-steps", type=int, default=10)
     ap.add_argument("--no-blast3d", action="store_true",
                     help="skip the 3D blast leg (256^3 grid, 134M particles), reported beside the line")
+    ap.add_argument("--only-blast3d", action="store_true",
+                    help="run the 3D blast leg alone and print its JSON object (profiling runs)")
+    ap.add_argument("--blast-profile-steps", type=int, default=-1,
+                    help="steps of the 3D per-sweep profile (-1: as many as timed, 0: none)")
     ap.add_argument("--blast-n", type=int, default=256)
     ap.add_argument("--blast-steps", type=int, default=100)
     ap.add_argument("--blast-warmup", type=int, default=16)
@@ -422,6 +426,9 @@ def main():
     from paper_2404_17057_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.only_blast3d:
+        print(json.dumps({"metric": "3D blast leg alone", **blast3d(args)}), flush=True)
+        return
     if args.ablation:
         print(json.dumps(ablation(args)), flush=True)
         return

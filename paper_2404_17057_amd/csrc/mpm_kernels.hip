@@ -204,8 +204,10 @@ __device__ __forceinline__ void s1_factors(const PP *P, const S1In<typename Prec
     }
 }
 
-// 3D FP32 S1: particles per tile whose scalars are kept in LDS (40 KiB)
-template <int DIM, typename R> constexpr uint32_t kS1CacheN = DIM == 3 && sizeof(R) == 4 ? 2048 : 0;
+// 3D FP32 S1: the first kS1CacheJ particles of every cell keep their scalars
+// in LDS (40 KiB); slot (j, lane) of field i is fcache[(i * J + j) * 256 +
+// lane], so the lanes of one access touch consecutive words
+template <int DIM, typename R> constexpr uint32_t kS1CacheJ = DIM == 3 && sizeof(R) == 4 ? 8 : 0;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
@@ -258,21 +260,28 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 
     // Next order: clear this tile's cell histogram and tile total (read by
     // nothing in this sweep, filled by S2).  3D, next step's grid: clear the
-    // frame nodes of this tile's footprint in the other buffer, which the
-    // flush adds to atomically (the owned nodes are overwritten by stores;
-    // in 2D the frame sums go through the halo records instead).
+    // frame nodes of the other buffer, which the flush adds to atomically
+    // (the owned nodes are overwritten by stores; in 2D the frame sums go
+    // through the halo records instead).  Each frame node is cleared once,
+    // by its designated tile: per axis the tile whose cells start at or below
+    // the node and end above it, min(g / T, ntile - 1), which holds the node
+    // in its footprint.
     gmem(P->count)[key] = 0;
     if (threadIdx.x == 0) gmem(P->ttot)[t] = 0;
     if constexpr (!kHalo<DIM>) {
         GLOBAL_AS A *gAn = gmem((A *)P->gA[par ^ 1]);
         GLOBAL_AS A *gBn = gmem((A *)P->gB[par ^ 1]);
         const long long NN = P->nnodes;
+        const int tx = c0[0] / G::TX, ty = c0[1] / G::TY, tz = c0[2] / G::TZ;
         for (int li = threadIdx.x; li < G::TN; li += kBlock) {
             const int ix = li % G::NX, iy = (li / G::NX) % G::NY, iz = li / (G::NX * G::NY);
             const bool own = ix >= G::W - 1 && ix < G::TX && iy >= G::W - 1 && iy < G::TY &&
                              (DIM == 2 || (iz >= G::W - 1 && iz < G::TZ));
             const int gx = c0[0] + ix, gy = c0[1] + iy, gz = c0[2] + iz;
             if (own || gx >= P->nn[0] || gy >= P->nn[1] || gz >= P->nn[2]) continue;
+            if (min(gx / G::TX, P->ntile[0] - 1) != tx || min(gy / G::TY, P->ntile[1] - 1) != ty ||
+                min(gz / G::TZ, P->ntile[2] - 1) != tz)
+                continue;
             const long long node = node_index(P, gx, gy, gz);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) gAn[q * NN + node] = (A)0;
@@ -281,11 +290,10 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
         }
     }
 
-    // 3D FP32: the per-particle scalars of the tile's first FC particles,
+    // 3D FP32: the per-particle scalars of each cell's first FJ particles,
     // computed by the first z-slab pass and read by the other two
-    constexpr uint32_t FC = kS1CacheN<DIM, R>;
-    __shared__ R fcache[FC > 0 ? 5 * FC : 1];
-    const uint32_t tb = off[(uint32_t)t * G::CELLS];
+    constexpr uint32_t FJ = kS1CacheJ<DIM, R>;
+    __shared__ R fcache[FJ > 0 ? 5 * FJ * kBlock : 1];
     // Each lane walks the particles of its cell; the fields of the next
     // particle are loaded while the current one is summed (the index is
     // clamped, so the last iteration reloads its own particle).
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
 
         // a particle whose scalars the first pass cached loads only X again
-        auto need = [&](int f, uint32_t kk) { return !(pass > 0 && f >= DIM && kk - tb < FC); };
+        auto need = [&](int f, uint32_t kk) { return !(pass > 0 && f >= DIM && kk - beg < FJ); };
         R cur[NPF];
 #pragma unroll
         for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
@@ -330,15 +338,15 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
             // the particle's scalars: computed, or in 3D cached by the first
             // pass for the other two
             R sc[5];
-            const uint32_t kl = k - tb;
-            if (pass > 0 && kl < FC) {
+            const uint32_t kj = k - beg;
+            if (pass > 0 && kj < FJ) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) sc[i] = fcache[i * FC + kl];
+                for (int i = 0; i < 5; ++i) sc[i] = fcache[(i * FJ + kj) * kBlock + threadIdx.x];
             } else {
                 s1_scalars<DIM, PREC>(&V, in, sc, own);
-                if (kl < FC)
+                if (kj < FJ)
 #pragma unroll
-                    for (int i = 0; i < 5; ++i) fcache[i * FC + kl] = sc[i];
+                    for (int i = 0; i < 5; ++i) fcache[(i * FJ + kj) * kBlock + threadIdx.x] = sc[i];
             }
             S1Factors<DIM, SHAPE, R> f;
             s1_products<DIM, SHAPE, R>(sc, st, f);
@@ -583,10 +591,11 @@ __device__ __forceinline__ void s2_key_rank(const PP *P, GLOBAL_AS uint32_t *cou
 }
 
 constexpr uint32_t kRankBuf = 2048;   // S2: rank words staged in LDS per tile
-// 3D FP32 S2: V' of the tile's first 2048 particles kept in LDS (24 KiB)
-// by the first z-slab pass for the other two (128^3 blast: S2 -7 %; with an
-// FP64 state the larger tile leaves it slower)
-template <int DIM, typename R> constexpr uint32_t kVCacheN = DIM == 3 && sizeof(R) == 4 ? 2048 : 0;
+// 3D FP32 S2: V' of each cell's first 8 particles kept in LDS (24 KiB) by
+// the first z-slab pass for the other two (with an FP64 state the larger
+// tile leaves it slower); slot (j, lane) of component a is
+// vcache[(a * J + j) * 256 + lane]
+template <int DIM, typename R> constexpr uint32_t kVCacheJ = DIM == 3 && sizeof(R) == 4 ? 8 : 0;
 
 template <int DIM, int SHAPE, int PREC>
 __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
@@ -653,8 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const uint32_t tb = off[(uint32_t)t * G::CELLS];
     const uint32_t tn = off[(uint32_t)(t + 1) * G::CELLS] - tb;
     __shared__ uint32_t rbuf[kRankBuf];
-    constexpr uint32_t VC = kVCacheN<DIM, R>;
-    __shared__ R vcache[VC > 0 ? DIM * VC : 1];
+    constexpr uint32_t VJ = kVCacheJ<DIM, R>;
+    __shared__ R vcache[VJ > 0 ? DIM * VJ * kBlock : 1];
     auto put_rank = [&](uint32_t k, uint32_t rk) {
         if (k - tb < kRankBuf) rbuf[k - tb] = rk;
         else stk(rankg, k, rk);
@@ -671,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 
         // V of a particle whose V' the first pass cached is not loaded again
         auto need = [&](int f, uint32_t kk) {
-            return !(pass > 0 && f >= DIM && f < 2 * DIM && kk - tb < VC);
+            return !(pass > 0 && f >= DIM && f < 2 * DIM && kk - beg < VJ);
         };
         R cur[NPF];
 #pragma unroll
@@ -698,18 +707,18 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             // is not stored (the update sweep recomputes it from the same
             // staged values, same bits).  In 3D the first pass keeps it in
             // LDS for the other two.
-            const uint32_t kl = k - tb;
-            if (pass > 0 && kl < VC) {
+            const uint32_t kj = k - beg;
+            if (pass > 0 && kj < VJ) {
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) v[a] = vcache[a * VC + kl];
+                for (int a = 0; a < DIM; ++a) v[a] = vcache[(a * VJ + kj) * kBlock + threadIdx.x];
             } else {
                 R dv[3];
                 g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, lc, dv);
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
-                if (kl < VC)
+                if (kj < VJ)
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) vcache[a * VC + kl] = v[a];
+                    for (int a = 0; a < DIM; ++a) vcache[(a * VJ + kj) * kBlock + threadIdx.x] = v[a];
             }
             if (pass == 0 && own) {
                 // G2P of vstar: the move, the new cell key and the rank
