@@ -403,6 +403,9 @@ def main():
     ap.add_argument("--blast-oracle-steps", type=int, default=4,
                     help="oracle steps of the 64^3 downscale for the accuracy figure, on all host "
                          "cores (0 = skip)")
+    ap.add_argument("--colouring", action="store_true",
+                    help="also time the FP64 state with the grid-colouring P2G (no atomics) beside the "
+                         "LDS-tile FP64 path, with per-sweep times")
     ap.add_argument("--all-precisions", action="store_true",
                     help="also time the FP32 state with FP64 and with FP32 accumulators on the same workload")
     ap.add_argument("--aerofoil", action="store_true",
@@ -444,6 +447,19 @@ def main():
         log(f"fp64: {fp64['ms_per_step']:.4f} ms/step, {fp64['value']:.4e} particle-steps/s")
 
     blast3d_leg = None if args.no_blast3d else blast3d(args)
+
+    # the grid-colouring P2G (atomic-free, bit-reproducible FP64) beside the
+    # LDS-tile FP64 path on the same workload and span
+    colouring = None
+    if args.colouring:
+        col = time_gpu(pb, G.FP64_COLOR, args.steps, args.warmup, args.profile_steps)
+        colouring = {"value": round(col["value"], 1), "ms_per_step": round(col["ms_per_step"], 5),
+                     "sweeps_ms": col["sweeps_ms"],
+                     "lds_tile_fp64": None if fp64 is None else {"value": round(fp64["value"], 1),
+                                                                "ms_per_step": round(fp64["ms_per_step"], 5),
+                                                                "sweeps_ms": fp64["sweeps_ms"]}}
+        log(f"fp64 colouring: {col['ms_per_step']:.4f} ms/step, {col['value']:.4e} particle-steps/s, "
+            f"sweeps {col['sweeps_ms']}")
 
     # the other two FP32-state modes (FP64 and FP32 accumulators) on the same
     # workload and span, for the precision ablation
@@ -615,6 +631,7 @@ def main():
         "host_inclusive": hostinc,
         "precision_modes": modes,
         "blast3d": blast3d_leg,
+        "colouring": colouring,
         "aerofoil": aerofoil(args) if args.aerofoil else None,
         "kernel_source_hash": src_hash,
     }

@@ -77,8 +77,15 @@ enum {
     MPM_FP64 = 0,          /* FP64 state, FP64 atomic accumulation              */
     MPM_FP32_ACC_F64 = 1,  /* FP32 state, FP64 atomic accumulation              */
     MPM_FP32_ACC_F32 = 2,  /* FP32 state, FP32 atomic accumulation              */
-    MPM_FP32_FIX64 = 3     /* FP32 state, 64-bit fixed-point integer accumulation:
+    MPM_FP32_FIX64 = 3,    /* FP32 state, 64-bit fixed-point integer accumulation:
                               sums are order-independent and bit-reproducible   */
+    MPM_FP64_COLOR = 4     /* FP64 state; each P2G by grid colouring (Sec. 5:
+                              cells coloured so that cells of one colour have
+                              disjoint stencils, 3^dim colours for B2), one
+                              pass per colour with plain adds and no atomics,
+                              every cell's particles summed in id order:
+                              bit-reproducible without fixed point.  B2 only
+                              (Q1: MPM_E_UNSUPPORTED)                          */
 };
 
 /* Domain face types (Sec. 4.1, eq. bc). */

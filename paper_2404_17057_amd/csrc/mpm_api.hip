@@ -84,15 +84,15 @@ int check_desc(const mpm_desc *d, double *h_out) {
     if (!d) return MPM_E_ARG;
     if (d->dim != 2 && d->dim != 3) return MPM_E_ARG;
     if (d->shape != MPM_Q1 && d->shape != MPM_B2) return MPM_E_ARG;
-    if (d->precision < MPM_FP64 || d->precision > MPM_FP32_FIX64) return MPM_E_ARG;
+    if (d->precision < MPM_FP64 || d->precision > MPM_FP64_COLOR) return MPM_E_ARG;
     if (d->av_form != MPM_AV_PAPER && d->av_form != MPM_AV_BOOK) return MPM_E_ARG;
     if (!(d->gamma > 1.0) || !(d->cfl > 0.0) || d->n_particles < 0) return MPM_E_ARG;
     // particle arrays are addressed with 32-bit byte offsets: each must stay
     // below 4 GiB
-    const long long real_sz = d->precision == MPM_FP64 ? 8 : 4;
+    const long long real_sz = (d->precision == MPM_FP64 || d->precision == MPM_FP64_COLOR) ? 8 : 4;
     if (d->n_particles * real_sz > 0xFFFFFFF0LL) return MPM_E_UNSUPPORTED;
     if (d->shape == MPM_Q1 && d->precision != MPM_FP64 && d->precision != MPM_FP32_FIX64)
-        return MPM_E_UNSUPPORTED;
+        return MPM_E_UNSUPPORTED;   // (the colouring is built for B2's 3^dim colours)
     double h = 0;
     for (int a = 0; a < d->dim; ++a) {
         if (d->n[a] < 2 || !(d->hi[a] > d->lo[a])) return MPM_E_ARG;
@@ -158,7 +158,7 @@ Layout make_layout(const mpm_desc *d) {
     }
     L.ncells_pad = (long long)L.ntiles * 256;
     L.nchunks = (int)((L.ncells_pad + kScanChunk - 1) / kScanChunk);
-    L.real_sz = d->precision == MPM_FP64 ? 8 : 4;
+    L.real_sz = (d->precision == MPM_FP64 || d->precision == MPM_FP64_COLOR) ? 8 : 4;
     L.acc_sz = d->precision == MPM_FP32_ACC_F32 ? 4 : 8;
     size_t o = 0;
     L.off_prob = o; o = align_up(o + sizeof(ProbDev));

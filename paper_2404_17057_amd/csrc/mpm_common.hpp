@@ -13,18 +13,20 @@
 namespace mpm {
 
 // -------------------------------------------------------------- precision --
-enum Prec { P_FP64 = 0, P_F32_A64 = 1, P_F32_A32 = 2, P_F32_FIX = 3 };
+enum Prec { P_FP64 = 0, P_F32_A64 = 1, P_F32_A32 = 2, P_F32_FIX = 3, P_FP64_COL = 4 };
 
 // real: particle state and node arithmetic; acc: global grid accumulators;
 // lacc: per-lane and LDS partial sums.  In the fixed-point precision every
 // contribution is rounded to a whole number of quanta before it is added, so
 // the partial sums are integers held exactly in FP64 (|sum| < 2^53) and the
-// global accumulators are int64.
+// global accumulators are int64.  colour: the P2G sums go through passes of
+// a grid colouring with plain adds (FP64 state; no atomics).
 template <int PREC> struct PrecT;
-template <> struct PrecT<P_FP64>    { using real = double; using acc = double;    using lacc = double; static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_A64> { using real = float;  using acc = double;    using lacc = double; static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_A32> { using real = float;  using acc = float;     using lacc = float;  static constexpr bool fixed = false; };
-template <> struct PrecT<P_F32_FIX> { using real = float;  using acc = long long; using lacc = double; static constexpr bool fixed = true;  };
+template <> struct PrecT<P_FP64>    { using real = double; using acc = double;    using lacc = double; static constexpr bool fixed = false; static constexpr bool colour = false; };
+template <> struct PrecT<P_F32_A64> { using real = float;  using acc = double;    using lacc = double; static constexpr bool fixed = false; static constexpr bool colour = false; };
+template <> struct PrecT<P_F32_A32> { using real = float;  using acc = float;     using lacc = float;  static constexpr bool fixed = false; static constexpr bool colour = false; };
+template <> struct PrecT<P_F32_FIX> { using real = float;  using acc = long long; using lacc = double; static constexpr bool fixed = true;  static constexpr bool colour = false; };
+template <> struct PrecT<P_FP64_COL> { using real = double; using acc = double;   using lacc = double; static constexpr bool fixed = false; static constexpr bool colour = true; };
 
 // ------------------------------------------------------------- constants --
 enum Shape { S_Q1 = 1, S_B2 = 2 };

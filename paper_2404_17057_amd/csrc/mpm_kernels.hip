@@ -606,6 +606,9 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     constexpr int W = G::W;
     constexpr int NF = stage_stride<DIM, false>();
     constexpr int ND = DestFoot<DIM>::N;
+    // the colouring precision does its P2G of M V' in colour passes after
+    // this sweep; here only the G2P of the move, the new cell and the rank
+    constexpr bool kP2G = !PrecT<PREC>::colour;
     // Particle fields read per particle: X[DIM], V[DIM], M (the id only for a
     // particle recycled at the outflow)
     constexpr int NPF = 2 * DIM + 1;
@@ -671,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     // Each lane walks the particles of its cell, loading the next
     // particle's fields while the current one is processed.
 #pragma unroll 1
-    for (int pass = 0; pass < G::PASSES; ++pass) {
+    for (int pass = 0; pass < (kP2G ? G::PASSES : 1); ++pass) {
         L acc[G::WP][DIM];
 #pragma unroll
         for (int s = 0; s < G::WP; ++s)
@@ -708,7 +711,9 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             // staged values, same bits).  In 3D the first pass keeps it in
             // LDS for the other two.
             const uint32_t kj = k - beg;
-            if (pass > 0 && kj < VJ) {
+            if (!kP2G) {
+                // V' is not needed here
+            } else if (pass > 0 && kj < VJ) {
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) v[a] = vcache[(a * VJ + kj) * kBlock + threadIdx.x];
             } else {
@@ -728,6 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                 s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
                 put_rank(k, rk);
             }
+            if constexpr (kP2G) {
             const R Ms = own ? cur[2 * DIM] * sp : (R)0;
             R px[3][W];
 #pragma unroll
@@ -746,10 +752,11 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += term<PREC>(px[a][jx], wyz, bias);
             }
+            }
 #pragma unroll
             for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
         }
-        if (end > beg) {
+        if (kP2G && end > beg) {
             const int lz = DIM == 3 ? lc[2] + pass : 0;
 #pragma unroll
             for (int jy = 0; jy < W; ++jy)
@@ -791,6 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
             s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{ids, k}, c0, hist, nk, rk, flags);
             put_rank(k, rk);
             const R Ms = Mp[k] * sp;
+            if (!kP2G) continue;
 #pragma unroll 1
             for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll 1
@@ -808,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     if (threadIdx.x < 27) ttl[threadIdx.x] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < min(tn, kRankBuf); i += kBlock) stk(rankg, tb + i, rbuf[i]);
-    flush_tile<DIM, SHAPE, PREC, DIM, false>(P, t, c0, tile, P->gB[par], P->haloB, flags);
+    if constexpr (kP2G) flush_tile<DIM, SHAPE, PREC, DIM, false>(P, t, c0, tile, P->gB[par], P->haloB, flags);
     // One global histogram atomic per destination cell of this tile: the
     // tile's particles of that cell get the ranks base .. base + hist - 1.
     // Tile totals are gathered per destination tile (the tile and its
@@ -835,6 +843,196 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     }
     if (flags & (ERR_OVERFLOW | ERR_INTERNAL)) atomicOr((uint32_t *)&P->err, flags & (ERR_OVERFLOW | ERR_INTERNAL));
     if (mismatch) atomicAdd((unsigned long long *)&P->diag[DG_MISMATCH], (unsigned long long)mismatch);
+}
+
+// ------------------------------------------------------ colouring P2G --
+// The P2G of the colouring precision (grid colouring, Sec. 5): a cell's B2
+// stencil spans W = 3 nodes per axis, so cells whose coordinates agree modulo
+// 3 have disjoint stencils.  One launch per colour; one thread per cell of
+// that colour sums its cell's particles, in increasing particle id (a
+// canonical order, whatever order the sort left), into registers and adds
+// the sums into the grid with plain loads and stores: no other thread of the
+// launch touches those nodes, and the launches of one P2G run in colour
+// order.  Sums are therefore bit-reproducible without fixed point.
+
+// Zeroes this step's grids (the colour passes add into them) and, like S1,
+// the cell histogram and tile totals of the next order.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_zero_grid(WorkTab wt) {
+    const int pi = find_prob(wt, blockIdx.x);
+    ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int t = blockIdx.x - wt.start[pi];
+    const int par = P->parity;
+    gmem(P->count)[(uint32_t)t * Tile<DIM>::CELLS + threadIdx.x] = 0;
+    if (threadIdx.x == 0) gmem(P->ttot)[t] = 0;
+    const long long na = (long long)(1 + 2 * DIM) * P->nnodes, nb = (long long)DIM * P->nnodes;
+    const long long per = (na + nb + P->ntiles - 1) / P->ntiles;
+    GLOBAL_AS double *ga = gmem((double *)P->gA[par]);
+    GLOBAL_AS double *gb = gmem((double *)P->gB[par]);
+    const long long i1 = min((long long)(t + 1) * per, na + nb);
+    for (long long i = (long long)t * per + threadIdx.x; i < i1; i += kBlock) {
+        if (i < na) ga[i] = 0.0;
+        else gb[i - na] = 0.0;
+    }
+}
+
+// One colour pass.  WHICH = 0: m, p and dt f of S1 into gA; WHICH = 1: the
+// P2G of M V' into gB, V' = V + dt A from the conditioned grid of S1 (the
+// same values and order as the gather sweeps).
+template <int DIM, int SHAPE, int PREC, int WHICH>
+__global__ __launch_bounds__(kBlock) void k_p2g_colour(WorkTab wt, int colour) {
+    using G = Geo<DIM, SHAPE>;
+    using R = typename PrecT<PREC>::real;
+    constexpr int W = G::W;
+    constexpr int NQ = WHICH == 0 ? 1 + 2 * DIM : DIM;
+    const int pi = find_prob(wt, blockIdx.x);
+    const ProbDev *P = wt.prob[pi];
+    if (!P->active) return;
+    const int col[3] = {colour % W, (colour / W) % W, DIM == 3 ? colour / (W * W) : 0};
+    int m[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) m[a] = P->n[a] > col[a] ? (P->n[a] - col[a] + W - 1) / W : 0;
+    const long long g = (long long)(blockIdx.x - wt.start[pi]) * kBlock + threadIdx.x;
+    if (g >= (long long)m[0] * m[1] * m[2]) return;
+    const int cell[3] = {col[0] + W * (int)(g % m[0]), col[1] + W * (int)((g / m[0]) % m[1]),
+                         DIM == 3 ? col[2] + W * (int)(g / ((long long)m[0] * m[1])) : 0};
+    const View V = make_view(P);
+    const int par = P->parity;
+    const GLOBAL_AS uint32_t *off = gmem((const uint32_t *)P->offs[par]);
+    const uint32_t key = cell_key<DIM>(P, cell);
+    const uint32_t beg = off[key], end = off[key + 1];
+    if (end == beg) return;
+    const GLOBAL_AS uint32_t *ids = gmem((const uint32_t *)P->pid[par]);
+    GLOBAL_AS double *grid = gmem((double *)(WHICH == 0 ? P->gA[par] : P->gB[par]));
+    const long long NN = P->nnodes;
+    uint32_t flags = 0;
+    // The order by id: for a cell of at most KMAX particles the ids are held
+    // in registers and ranked there; a fuller cell is scanned in global
+    // memory for each next id.
+    constexpr int KMAX = 16;
+    const uint32_t n = end - beg;
+    uint32_t idr[KMAX], rk[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) idr[j] = (uint32_t)j < n ? ids[beg + j] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) r += idr[i] < idr[j] ? 1u : 0u;
+        rk[j] = r;
+    }
+    // 2D, the P2G of M V': the cell's W x W conditioned nodes, staged once
+    // (dt f / m), summed as the gather sweeps sum them
+    R dvn[DIM == 2 && WHICH == 1 ? G::WP : 1][DIM];
+    if constexpr (DIM == 2 && WHICH == 1) {
+#pragma unroll
+        for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < W; ++jx) {
+                R vs[3], dv[3];
+                stage_A<DIM, PREC>(P, node_index(P, cell[0] + jx, cell[1] + jy, 0), vs, dv, flags);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) dvn[jy * W + jx][a] = dv[a];
+            }
+    }
+#pragma unroll 1
+    for (int pass = 0; pass < G::PASSES; ++pass) {
+        double acc[G::WP][NQ];
+#pragma unroll
+        for (int s = 0; s < G::WP; ++s)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[s][q] = 0.0;
+        uint32_t prev = 0;
+#pragma unroll 1
+        for (uint32_t r = 0; r < n; ++r) {
+            uint32_t k = beg;
+            if (n <= (uint32_t)KMAX) {
+#pragma unroll
+                for (int j = 0; j < KMAX; ++j) k += rk[j] == r ? (uint32_t)j : 0u;
+            } else {
+                uint32_t best = 0xFFFFFFFFu;
+                for (uint32_t j = beg; j < end; ++j) {
+                    const uint32_t id = ids[j];
+                    if ((r == 0 || id > prev) && id <= best) { best = id; k = j; }
+                }
+                prev = best;
+            }
+            R x[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) x[a] = gmem((const R *)P->part[par][PF_X + a])[k];
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R>(&V, x, st);
+            if (st.c[0] != cell[0] || st.c[1] != cell[1] || (DIM == 3 && st.c[2] != cell[2])) {
+                // a particle outside the cell it was sorted into would add to
+                // another thread's nodes: refused (the sort and the stencil
+                // compute the cell by the same expression, so never seen)
+                flags |= ERR_INTERNAL;
+                continue;
+            }
+            const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
+            if constexpr (WHICH == 0) {
+                S1Factors<DIM, SHAPE, R> f;
+                s1_factors<DIM, SHAPE, PREC>(&V, s1_load_global<DIM, R>(P, par, k), st, f);
+                const R dwz = DIM == 3 ? pick<W, R>(st.dw[2], pass) : (R)0;
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy) {
+                    const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
+                    const R dyz = DIM == 3 ? st.dw[1][jy] * wz : st.dw[1][jy];
+                    const R ydz = st.w[1][jy] * dwz;
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx) {
+                        double *ac = acc[jy * W + jx];
+                        ac[0] += f.mx[jx] * wyz;
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) ac[1 + a] += f.px[a][jx] * wyz;
+                        ac[1 + DIM] += f.fx[jx] * wyz;
+                        ac[2 + DIM] += f.gx[jx] * dyz;
+                        if constexpr (DIM == 3) ac[3 + DIM] += f.gx[jx] * ydz;
+                    }
+                }
+            } else {
+                R dv[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+                if constexpr (DIM == 2) {
+                    // the G2P of dt f / m row by row, as g2p_field
+#pragma unroll
+                    for (int jy = 0; jy < W; ++jy) {
+                        R row[3] = {0, 0, 0};
+#pragma unroll
+                        for (int jx = 0; jx < W; ++jx)
+#pragma unroll
+                            for (int a = 0; a < DIM; ++a) row[a] += st.w[0][jx] * dvn[jy * W + jx][a];
+                        const R wyz = st.w[1][jy];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) dv[a] += wyz * row[a];
+                    }
+                } else {
+                    R vbar[3], Gd[9];
+                    g2p_global<DIM, SHAPE, PREC, false>(P, st, vbar, dv, Gd, flags);
+                }
+                const R M = gmem((const R *)P->part[par][PF_M])[k];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) v[a] = gmem((const R *)P->part[par][PF_V + a])[k] + dv[a];
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy) {
+                    const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx)
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += ((M * v[a]) * st.w[0][jx]) * wyz;
+                }
+            }
+        }
+#pragma unroll
+        for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < W; ++jx) {
+                const long long node = node_index(P, cell[0] + jx, cell[1] + jy, DIM == 3 ? cell[2] + pass : 0);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) grid[q * NN + node] += acc[jy * W + jx][q];
+            }
+    }
+    if (flags & ERR_INTERNAL) atomicOr((uint32_t *)&P->err, ERR_INTERNAL);
 }
 
 // Wave-level reductions over the 64 lanes of a wavefront.
@@ -1055,7 +1253,7 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     }
     out[c] = base + ex;
     if (t == P->ntiles - 1 && threadIdx.x == 0) out[P->ncells_pad] = base + total;
-    if constexpr (kHalo<DIM>) {
+    if constexpr (kHalo<DIM> && !PrecT<PREC>::colour) {
         using R = typename PrecT<PREC>::real;
         using A = typename PrecT<PREC>::acc;
         reduce_frame<SHAPE, PREC, DIM, false>(P, t, gmem((R *)P->gB[P->parity]), gmem((const A *)P->haloB));
@@ -1659,13 +1857,29 @@ static inline dim3 grid1(int n) { return dim3((unsigned)n); }
 template <int DIM, int SHAPE, int PREC>
 void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
     const dim3 grid(tiles.start[tiles.n]);
+    // colouring precision: colour passes of at most one thread per cell, over
+    // the tile grid of workgroups (more than the cells of one colour need)
+    constexpr int kColours = Geo<DIM, SHAPE>::W * Geo<DIM, SHAPE>::W * (DIM == 3 ? Geo<DIM, SHAPE>::W : 1);
     switch (part) {
-    case 0: hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 0:
+        if constexpr (PrecT<PREC>::colour) {
+            hipLaunchKernelGGL((k_zero_grid<DIM>), grid, dim3(kBlock), 0, s, tiles);
+            for (int c = 0; c < kColours; ++c)
+                hipLaunchKernelGGL((k_p2g_colour<DIM, SHAPE, PREC, 0>), grid, dim3(kBlock), 0, s, tiles, c);
+        } else {
+            hipLaunchKernelGGL((k_p2g<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles);
+        }
+        break;
     case 1:
-        if (kHalo<DIM>)
+        if (kHalo<DIM> && !PrecT<PREC>::colour)
             hipLaunchKernelGGL((k_frame_reduce<DIM, SHAPE, PREC>), grid, dim3(Frame2<SHAPE>::NFR), 0, s, tiles);
         break;
-    case 2: hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles); break;
+    case 2:
+        hipLaunchKernelGGL((k_g2p<DIM, SHAPE, PREC>), grid, dim3(kBlock), 0, s, tiles);
+        if constexpr (PrecT<PREC>::colour)
+            for (int c = 0; c < kColours; ++c)
+                hipLaunchKernelGGL((k_p2g_colour<DIM, SHAPE, PREC, 1>), grid, dim3(kBlock), 0, s, tiles, c);
+        break;
     case 3:
         if (tiles.max_tiles > kFuseTiles) hipLaunchKernelGGL(k_tilescan, dim3(single.n), dim3(1024), 0, s, single);
         break;
@@ -1718,6 +1932,7 @@ void launch_grid_diag_t(ProbDev *dP, const ProbDev &h, int which, double *out, h
             case P_FP64: CALL(2, S_B2, P_FP64); break;                            \
             case P_F32_A64: CALL(2, S_B2, P_F32_A64); break;                      \
             case P_F32_A32: CALL(2, S_B2, P_F32_A32); break;                      \
+            case P_FP64_COL: CALL(2, S_B2, P_FP64_COL); break;                  \
             default: CALL(2, S_B2, P_F32_FIX); break;                             \
             }                                                                     \
         } else if ((DIMV) == 3 && (SHAPEV) == S_B2) {                             \
@@ -1725,6 +1940,7 @@ void launch_grid_diag_t(ProbDev *dP, const ProbDev &h, int which, double *out, h
             case P_FP64: CALL(3, S_B2, P_FP64); break;                            \
             case P_F32_A64: CALL(3, S_B2, P_F32_A64); break;                      \
             case P_F32_A32: CALL(3, S_B2, P_F32_A32); break;                      \
+            case P_FP64_COL: CALL(3, S_B2, P_FP64_COL); break;                  \
             default: CALL(3, S_B2, P_F32_FIX); break;                             \
             }                                                                     \
         } else if ((DIMV) == 2) {                                                 \

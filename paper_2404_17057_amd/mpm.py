@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libmpm.so")
 OK, E_ARG, E_WORKSPACE, E_HIP, E_NONPHYSICAL, E_OVERFLOW, E_UNSUPPORTED, E_STATE, E_SCRATCH = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 Q1, B2 = 1, 2
-FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64 = 0, 1, 2, 3
+FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64, FP64_COLOR = 0, 1, 2, 3, 4
 PRECISION_NAMES = {FP64: "fp64", FP32_ACC_F64: "fp32_acc_f64",
-                   FP32_ACC_F32: "fp32_acc_f32", FP32_FIX64: "fp32_fix64"}
+                   FP32_ACC_F32: "fp32_acc_f32", FP32_FIX64: "fp32_fix64", FP64_COLOR: "fp64_color"}
 F_X, F_V, F_M, F_RHO, F_E, F_P, F_Q, F_G, F_VOL, F_ID = range(10)
 G_M, G_P, G_F, G_PUPD, G_P2, G_FBC, G_FLAGS, G_MPROJ, G_VOLPROJ = range(9)
 

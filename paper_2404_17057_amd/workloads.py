@@ -37,7 +37,7 @@ import numpy as np
 WALL, INFLOW, OUTFLOW = 0, 1, 2
 Q1, B2 = 1, 2
 AV_PAPER, AV_BOOK = 0, 1
-FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64 = 0, 1, 2, 3
+FP64, FP32_ACC_F64, FP32_ACC_F32, FP32_FIX64, FP64_COLOR = 0, 1, 2, 3, 4
 
 DEFAULT_SEED = 17057
 
