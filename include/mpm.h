@@ -88,7 +88,14 @@ enum {
                               (Q1: MPM_E_UNSUPPORTED)                          */
 };
 
-/* Domain face types (Sec. 4.1, eq. bc). */
+/* Domain face types (Sec. 4.1, eq. bc).  WALL: the normal momentum and force
+ * of the face's nodes are set to 0.  INFLOW: momentum m u_in, force 0.
+ * OUTFLOW: no condition; a particle leaving through it is regenerated at the
+ * inflow boundary with the inflow state (Sec. 4.1): through x_hi it is
+ * shifted back by the domain length, through a y or z face it re-enters at
+ * x_lo as far past it as it went past the face it left; its transverse
+ * coordinates come from a hash of (seed, step, id).  An OUTFLOW face needs
+ * x_lo to be INFLOW and cannot be x_lo (else MPM_E_UNSUPPORTED). */
 enum { MPM_FACE_WALL = 0, MPM_FACE_INFLOW = 1, MPM_FACE_OUTFLOW = 2 };
 
 /* Artificial viscosity (Sec. 2.1, eq. muart): as printed,

@@ -635,16 +635,31 @@ static int one_step(orc_state *s) {
     }
 
     /* (ix) Postponed move with the G2P velocity: X' = X + dt Vbar.
-     * Outflow: the particle re-enters at the inflow face, its transverse
-     * coordinates drawn from a counter hash of (seed, step, id), with the
-     * inflow state.  Reading of "a random cell at the inflow boundary". */
+     * Outflow (Sec. 4.1: a particle leaving through an outflow face is
+     * regenerated in a random cell at the inflow boundary, with the inflow
+     * state): the particle re-enters at the x_lo inflow face, as far past
+     * it as it went past the face it left (through x_hi: shifted back by the
+     * domain length), its transverse coordinates drawn from a counter hash
+     * of (seed, step, id). */
     int64_t escapes = 0;
 #pragma omp parallel for num_threads(nt) if (nt > 1) reduction(+ : escapes)
     for (int64_t k = 0; k < s->np; ++k) {
         for (int a = 0; a < dim; ++a) s->x[a][k] += dt * s->vbar[a][k];
         int recycled = 0;
-        if (pb->face[0][1] == ORC_FACE_OUTFLOW && s->x[0][k] >= pb->hi[0]) {
-            s->x[0][k] -= (pb->hi[0] - pb->lo[0]);
+        /* the outflow face it crossed, if any (x_hi first, then lo/hi of y, z) */
+        int out_axis = -1;
+        double past = 0.0;
+        if (pb->face[0][1] == ORC_FACE_OUTFLOW && s->x[0][k] >= pb->hi[0]) out_axis = 0;
+        for (int a = 1; a < dim && out_axis < 0; ++a) {
+            if (pb->face[a][0] == ORC_FACE_OUTFLOW && s->x[a][k] < pb->lo[a]) {
+                out_axis = a; past = pb->lo[a] - s->x[a][k];
+            } else if (pb->face[a][1] == ORC_FACE_OUTFLOW && s->x[a][k] >= pb->hi[a]) {
+                out_axis = a; past = s->x[a][k] - pb->hi[a];
+            }
+        }
+        if (out_axis >= 0) {
+            if (out_axis == 0) s->x[0][k] -= (pb->hi[0] - pb->lo[0]);
+            else s->x[0][k] = pb->lo[0] + past;
             for (int a = 1; a < dim; ++a) {
                 uint64_t word = pb->seed ^ ((uint64_t)s->step << 32) ^ (uint64_t)k ^
                                 ((uint64_t)(a - 1) << 56);

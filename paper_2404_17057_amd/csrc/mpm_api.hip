@@ -101,9 +101,14 @@ int check_desc(const mpm_desc *d, double *h_out) {
         else if (fabs(ha - h) > 1e-9 * h) return MPM_E_ARG;
         for (int s = 0; s < 2; ++s)
             if (d->face[a][s] < MPM_FACE_WALL || d->face[a][s] > MPM_FACE_OUTFLOW) return MPM_E_ARG;
-        if (d->face[a][0] == MPM_FACE_OUTFLOW || (a > 0 && d->face[a][1] == MPM_FACE_OUTFLOW))
-            return MPM_E_UNSUPPORTED;   // outflow (recycling) only at the high-x face
     }
+    // particles leaving through an outflow face re-enter at the x_lo face,
+    // which must then be the inflow face (and cannot itself be an outflow)
+    for (int a = 0; a < d->dim; ++a)
+        for (int s = 0; s < 2; ++s)
+            if (d->face[a][s] == MPM_FACE_OUTFLOW &&
+                ((a == 0 && s == 0) || d->face[0][0] != MPM_FACE_INFLOW))
+                return MPM_E_UNSUPPORTED;
     // an INFLOW face imposes, and recycling through an OUTFLOW face
     // regenerates particles with, the inflow state: it must be physical
     bool inflow = false, outflow = false;

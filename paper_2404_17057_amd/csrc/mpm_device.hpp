@@ -323,8 +323,26 @@ template <int DIM, typename R, class PP, class ID>
 __device__ __forceinline__ int advect(const PP *P, R x[3], const R vbar[3], R dt, const ID &id) {
 #pragma unroll
     for (int a = 0; a < DIM; ++a) x[a] = x[a] + dt * vbar[a];
-    if (P->face[0][1] == F_OUTFLOW && x[0] >= (R)P->hi[0]) {
-        x[0] = x[0] - (R)(P->hi[0] - P->lo[0]);
+    // Outflow: through x_hi the particle is shifted back by the domain
+    // length; through a y / z outflow face it re-enters at the x_lo inflow
+    // face as far past it as it went past the face it left.  The transverse
+    // coordinates come from the recycling hash.
+    int out_axis = -1;
+    R past = 0;
+    if (P->face[0][1] == F_OUTFLOW && x[0] >= (R)P->hi[0]) out_axis = 0;
+#pragma unroll
+    for (int a = 1; a < DIM; ++a) {
+        if (out_axis >= 0) break;
+        if (P->face[a][0] == F_OUTFLOW && x[a] < (R)P->lo[a]) {
+            out_axis = a;
+            past = (R)P->lo[a] - x[a];
+        } else if (P->face[a][1] == F_OUTFLOW && x[a] >= (R)P->hi[a]) {
+            out_axis = a;
+            past = x[a] - (R)P->hi[a];
+        }
+    }
+    if (out_axis >= 0) {
+        x[0] = out_axis == 0 ? x[0] - (R)(P->hi[0] - P->lo[0]) : (R)P->lo[0] + past;
 #pragma unroll
         for (int a = 1; a < DIM; ++a) {
             const unsigned long long word = P->seed ^ ((unsigned long long)P->step << 32) ^

@@ -336,8 +336,8 @@ def aerofoil(nx=640, per_axis=2, mach=0.73, code="2412", alpha_deg=-3.5, chord=0
     come from the sampled signed distance (`sdf_obstacle`).  A NACA
     4-digit section stands in for the OAT15a profile, whose coordinates are
     not available.  Inflow at x_lo with u = (mach, 0) in gas with rho = 1.4,
-    p = 1 (so c = 1), outflow (recycling) at x_hi; the y faces are slip
-    walls, as outflow is only supported on the x_hi face."""
+    p = 1 (so c = 1), outflow (recycling) at the other three faces, as in
+    Sec. 4.1."""
     h = 0.4 / nx
     ny = int(round(0.27 / h))
     n = (nx, ny, 1)
@@ -355,7 +355,7 @@ def aerofoil(nx=640, per_axis=2, mach=0.73, code="2412", alpha_deg=-3.5, chord=0
     v[0] = mach
     return Problem(
         name=f"aerofoil_naca{code}_{nx}x{ny}_ppc{ppc}", dim=2, n=n, lo=lo, hi=hi,
-        faces=((INFLOW, OUTFLOW), (WALL, WALL), (WALL, WALL)),
+        faces=((INFLOW, OUTFLOW), (OUTFLOW, OUTFLOW), (WALL, WALL)),
         x=x, v=v, mass=np.full(N, m0), rho=np.full(N, rho0),
         eint=np.full(N, p0 / ((gamma - 1.0) * rho0)), ids=np.arange(N, dtype=np.uint32),
         shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
@@ -474,6 +474,18 @@ def linear_flow_box(A, gprev=None, n=12, rho=1.0, p=1.0) -> Problem:
     if gprev is not None:
         pb.gradv = np.repeat(np.asarray(gprev, np.float64).reshape(4, 1), pb.n_particles, axis=1)
     pb.name = f"linear_flow_{n}"
+    return pb
+
+
+def outflow_drift(n=8, u=(0.1, 0.5)) -> Problem:
+    """Pressureless gas on a regular 2x2 lattice moving uniformly with u;
+    inflow (with the same u) at x_lo, outflow at the other three faces.  A
+    time step that carries the top row through the y_hi face recycles it."""
+    pb = uniform_box(dim=2, n=n, jitter=0.0, rho=1.0, p=0.0, u=(u[0], u[1], 0.0),
+                     faces=((INFLOW, OUTFLOW), (OUTFLOW, OUTFLOW), (WALL, WALL)))
+    pb.inflow_rho, pb.inflow_p, pb.inflow_u = 1.0, 0.0, (u[0], u[1], 0.0)
+    pb.recycle_mass = float(pb.mass[0])
+    pb.name = f"outflow_drift_{n}"
     return pb
 
 

@@ -171,3 +171,26 @@ def test_projected_density_matches_oracle(prec, tol):
     assert np.abs(m - m_o).max() <= tol * m_o.max()
     assert np.abs(v - v_o).max() <= tol * v_o.max()
     assert np.array_equal(m > 0, m_o > 0)
+
+
+@pytest.mark.parametrize("prec", [G.FP64, G.FP32_FIX64])
+def test_recycling_through_a_y_outflow_face(prec):
+    """The same step as the oracle pin: the top row leaves through the y_hi
+    outflow face and re-enters at the inflow face; positions against the
+    oracle, recycled count from the counters."""
+    _gpu()
+    pb = W.outflow_drift(n=8)
+    pb.dt0 = 0.6 * pb.h
+    o = O.Oracle(pb)
+    o.set_dt(pb.dt0)
+    assert o.step(1) == 0
+    print(f"y outflow recycling prec {prec}", flush=True)
+    s = G.Simulation(pb, prec)
+    s.step(1)
+    assert s.status()["rc"] == 0
+    assert int(s.counters()[2]) == 16 and int(s.counters()[1]) == 0
+    x = s.field(G.F_X)
+    tol = 1e-12 if prec == G.FP64 else 2e-7
+    assert np.abs(x - o.particles(O.F_X)).max() <= tol
+    assert np.array_equal(s.field(G.F_M), o.particles(O.F_M).astype(np.float32).astype(np.float64)
+                          if prec == G.FP32_FIX64 else o.particles(O.F_M))

@@ -249,7 +249,11 @@ def test_aerofoil_sdf_obstacle_run_against_oracle(prec, tol):
     s.step(40)
     st = s.status()
     assert st["rc"] == 0 and st["step"] == 40
-    assert st["t"] == pytest.approx(o.status()["t"], rel=1e-6)
+    # t is the sum of the time steps; each comes from the state of its step,
+    # which the FP32 path holds within 2e-5 relative (a few tens of FP32
+    # roundings); with outflow at the top and bottom the fastest particles
+    # sit in the gas expanding through those faces
+    assert st["t"] == pytest.approx(o.status()["t"], rel=1e-6 if prec == G.FP64 else 2e-5)
     assert rel_l1(s.field(G.F_RHO), o.particles(O.F_RHO)) <= tol
     assert rel_l1(s.field(G.F_E), o.particles(O.F_E)) <= tol
     assert rel_l1(s.field(G.F_V), o.particles(O.F_V)) <= tol

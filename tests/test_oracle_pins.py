@@ -489,6 +489,34 @@ def test_wall_escape_is_clamped_and_counted():
     assert o.particles(O.F_RHO)[0] == pytest.approx(1.0 / (1.0 - 0.65 * 1.4), rel=1e-13)
 
 
+def test_recycling_through_a_y_outflow_face():
+    """Sec. 4.1: particles leaving through any outflow face are regenerated
+    at the inflow boundary with the inflow state.  A pressureless gas in
+    uniform motion u = (0.1, 0.5) (the G2P reproduces u exactly) and a step
+    dt = 0.6 h carry the top half of the top row (y = 1 - h/4) through the
+    y_hi outflow face by 0.05 h: each re-enters at x = x_lo + 0.05 h (as far
+    past the inflow face as it went past the face it left), with y drawn from
+    the hash; nothing else moves out, and the mass stays constant."""
+    pb = W.outflow_drift(n=8)
+    h, dt = pb.h, 0.6 * pb.h
+    o = O.Oracle(pb)
+    o.set_dt(dt)
+    assert o.step(1) == 0
+    x = o.particles(O.F_X)
+    top = pb.x[1] + dt * 0.5 >= 1.0
+    assert top.sum() == 16
+    for k in np.nonzero(top)[0]:
+        past = pb.x[1, k] + dt * 0.5 - 1.0
+        assert x[0, k] == pytest.approx(past, abs=1e-15)
+        assert past == pytest.approx(0.05 * h, rel=1e-9)
+        word = (pb.seed ^ (0 << 32) ^ int(k)) & 0xFFFFFFFFFFFFFFFF
+        assert x[1, k] == pytest.approx((O.splitmix64(word) >> 11) * 2.0 ** -53, abs=1e-15)
+    stay = ~top
+    assert np.abs(x[:, stay] - (pb.x[:, stay] + dt * np.array([[0.1], [0.5]]))).max() < 1e-15
+    assert np.array_equal(o.particles(O.F_M), pb.mass)
+    assert o.status()["wall_escapes"] == 0
+
+
 # ------------------------------------------------------------------- Sod --
 
 def test_exact_riemann_solver_against_tabulated_star_state():
