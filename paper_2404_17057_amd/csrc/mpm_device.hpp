@@ -36,8 +36,10 @@ template <int DIM, int SHAPE> struct Geo {
 // uniform pieces (1-u)^2/2, 1/2 + u(1-u), u^2/2.  The knot multiplicity
 // changes the pieces in the first cell, (1-u)^2, u(2 - 3u/2), u^2/2, and
 // symmetrically in the last cell, so that only the first (last) function is
-// non-zero on the domain face.
-template <int SHAPE, typename R>
+// non-zero on the domain face.  EDGE = false: the caller knows the cell is
+// neither the first nor the last (an interior tile), and only the uniform
+// pieces are evaluated.
+template <int SHAPE, typename R, bool EDGE = true>
 __device__ __forceinline__ int basis1(R s, int n, R w[3], R dw[3]) {
     int c = (int)floor(s);
     c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
@@ -46,6 +48,10 @@ __device__ __forceinline__ int basis1(R s, int n, R w[3], R dw[3]) {
     if constexpr (SHAPE == S_Q1) {
         w[0] = v;  dw[0] = (R)-1;
         w[1] = u;  dw[1] = (R)1;
+    } else if constexpr (!EDGE) {
+        w[0] = (R)0.5 * v * v;   dw[0] = -v;
+        w[1] = (R)0.5 + u * v;   dw[1] = (R)1 - (R)2 * u;
+        w[2] = (R)0.5 * u * u;   dw[2] = u;
     } else {
         // interior pieces, then the first / last cell by selection (no branches)
         const bool first = c == 0, last = c == n - 1;
@@ -116,13 +122,13 @@ template <int DIM, int SHAPE, typename R> struct Stencil {
     R w[3][3], dw[3][3];
 };
 
-template <int DIM, int SHAPE, typename R, class PP>
+template <int DIM, int SHAPE, typename R, bool EDGE = true, class PP>
 __device__ __forceinline__ void make_stencil(const PP *P, const R x[3], Stencil<DIM, SHAPE, R> &st) {
     const R inv_h = (R)P->inv_h;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const R s = (x[a] - (R)P->lo[a]) * inv_h;
-        st.c[a] = basis1<SHAPE, R>(s, P->n[a], st.w[a], st.dw[a]);
+        st.c[a] = basis1<SHAPE, R, EDGE>(s, P->n[a], st.w[a], st.dw[a]);
     }
     if constexpr (DIM == 2) st.c[2] = 0;
 }
@@ -158,38 +164,63 @@ __device__ __forceinline__ R art_visc(int form, R c0, R c1, R gamma, R h, R rho,
 // rounded to whole quanta before any addition, so every partial sum is an
 // integer and exact in FP64.
 //
-// A contribution is the product a*b of two real factors (e.g. M w_x and
-// w_y).  In the fixed-point precision the exact product (two FP32 numbers
-// multiply exactly in FP64) is rounded to the nearest whole quantum, ties to
-// even.  fma(a, b, B) with B = +-1.5 * 2^52 computes the product and that
-// rounding in one instruction: for |a b| < 2^51 the result is B + round(a b)
-// exactly, and the rounding depends on a b alone.  A per-cell partial sum
-// takes the terms of successive particles with alternating signs of B, so
-// it holds the exact integer sum, plus B after an odd number of particles;
-// `unbias` removes that at the end.  Every step stays below 2^53 in
-// magnitude, so no addition rounds.
+// A contribution is the product a*b of two FP32 factors (e.g. M w_x and
+// w_y).  A per-lane partial sum holds B + S, with S the integer sum in quanta
+// and B = 1.5 * 2^52, and a contribution is added by one FP64 FMA,
+// fma(a, b', B + S), where b' is b in FP64 with the lowest bit of its
+// significand set (fix_weight).  Why that is exact and order-free:
+//   a = A 2^alpha with A < 2^24 an integer (FP32), b' = Bo 2^beta with Bo an
+//   odd 53-bit integer, so the lowest set bit of a b' = A Bo 2^(alpha+beta)
+//   is 2^(alpha+beta+tz(A)) <= |a b'| / 2^52, below 1/2 while |a b'| < 2^51.
+//   a b' is then never an odd multiple of 1/2, B + S + a b' (in [2^52, 2^53),
+//   where the doubles are exactly the integers) is never halfway between two
+//   of them, and round-to-nearest yields B + S + round(a b') for every
+//   integer S.
+// b' exceeds |b| by at most one FP64 ulp (2^-52 relative), less than the
+// spacing of the exact FP32 products, so round(a b') is round(a b) with
+// exact halves rounded away from zero: symmetric under a -> -a, as the
+// mirror symmetries of a problem need.  (Without the odd bit one FMA would
+// round an exact half by the parity of S, i.e. by the order of the
+// additions.)  |S| stays below 2^51.
 constexpr double kFixBias = 6755399441055744.0;     // 1.5 * 2^52
 
-template <int PREC>
-__device__ __forceinline__ typename PrecT<PREC>::lacc term(typename PrecT<PREC>::real a, typename PrecT<PREC>::real b,
-                                                           double bias) {
-    if constexpr (PrecT<PREC>::fixed) return fma((double)a, (double)b, bias);
-    else return (typename PrecT<PREC>::lacc)(a * b);
+__device__ __forceinline__ double fix_weight(float b) {
+    return __longlong_as_double(__double_as_longlong((double)b) | 1LL);
 }
 
-// Bias of the n-th particle of a partial sum, and the final correction.
-__device__ __forceinline__ double term_bias(uint32_t n) { return (n & 1u) ? -kFixBias : kFixBias; }
+// Start value of a partial sum, and the sum it holds.
+template <int PREC> __device__ __forceinline__ typename PrecT<PREC>::lacc acc_zero() {
+    return PrecT<PREC>::fixed ? (typename PrecT<PREC>::lacc)kFixBias : (typename PrecT<PREC>::lacc)0;
+}
 template <int PREC>
-__device__ __forceinline__ typename PrecT<PREC>::lacc unbias(typename PrecT<PREC>::lacc s, uint32_t count) {
-    if constexpr (PrecT<PREC>::fixed) return (count & 1u) ? s - kFixBias : s;
+__device__ __forceinline__ typename PrecT<PREC>::lacc unbias(typename PrecT<PREC>::lacc s) {
+    if constexpr (PrecT<PREC>::fixed) return s - kFixBias;
     else return s;
 }
 
-// One contribution on its own (no running bias): the same integer as term().
+// Weight factor of the contributions (fixed point: b' above).
+template <int PREC> struct WeightT {
+    using type = typename std::conditional<PrecT<PREC>::fixed, double, typename PrecT<PREC>::real>::type;
+};
+template <int PREC>
+__device__ __forceinline__ typename WeightT<PREC>::type weight(typename PrecT<PREC>::real b) {
+    if constexpr (PrecT<PREC>::fixed) return fix_weight(b);
+    else return b;
+}
+
+// Partial sum s plus the contribution a*b (b from weight()).
+template <int PREC>
+__device__ __forceinline__ typename PrecT<PREC>::lacc accum(typename PrecT<PREC>::lacc s, typename PrecT<PREC>::real a,
+                                                            typename WeightT<PREC>::type b) {
+    if constexpr (PrecT<PREC>::fixed) return fma((double)a, b, s);
+    else return s + (typename PrecT<PREC>::lacc)(a * b);
+}
+
+// One contribution on its own: the same integer as the accumulated form.
 template <int PREC>
 __device__ __forceinline__ typename PrecT<PREC>::lacc term_exact(typename PrecT<PREC>::real a,
                                                                  typename PrecT<PREC>::real b) {
-    if constexpr (PrecT<PREC>::fixed) return fma((double)a, (double)b, kFixBias) - kFixBias;
+    if constexpr (PrecT<PREC>::fixed) return fma((double)a, fix_weight(b), kFixBias) - kFixBias;
     else return (typename PrecT<PREC>::lacc)(a * b);
 }
 

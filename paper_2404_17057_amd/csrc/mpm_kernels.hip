@@ -56,6 +56,20 @@ __device__ __forceinline__ void tile_cell(const ProbDev *P, int t, int c0[3], in
     lc[0] = l % TX; lc[1] = (l / TX) % TY; lc[2] = DIM == 3 ? l / (TX * TY) : 0;
 }
 
+// A tile none of whose cells is the first or last of an axis: the B2
+// stencils of its particles take only the uniform pieces (bit for bit the
+// values the general form gives there).  A particle whose cell lies outside
+// the tile is summed by the general code of each sweep.
+template <int DIM, int SHAPE>
+__device__ __forceinline__ bool tile_interior(const View &V, const int c0[3]) {
+    if constexpr (SHAPE != S_B2) return false;
+    constexpr int T[3] = {Tile<DIM>::X, Tile<DIM>::Y, Tile<DIM>::Z};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) in = in && c0[a] >= 1 && c0[a] + T[a] <= V.n[a] - 1;
+    return in;
+}
+
 // Footprint flush of an LDS partial-sum tile, one value per thread and
 // pass (q-major).  Nodes that only this tile's cells reach (local index
 // W-1 .. T-1 on every axis) are stored into the grid.  The frame shared with
@@ -247,6 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
 
     int c0[3], lc0[3];
     tile_cell<DIM>(P, t, c0, lc0);
+    const bool interior = tile_interior<DIM, SHAPE>(V, c0);
     const bool valid = c0[0] + lc0[0] < P->n[0] && c0[1] + lc0[1] < P->n[1] &&
                        (DIM == 2 || c0[2] + lc0[2] < P->n[2]);
     const int par = P->parity;
@@ -297,96 +312,102 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     // Each lane walks the particles of its cell; the fields of the next
     // particle are loaded while the current one is summed (the index is
     // clamped, so the last iteration reloads its own particle).
+    // The particle loop, compiled once for interior tiles (uniform B2
+    // pieces only) and once for tiles at a domain face.
+    auto sweep = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
 #pragma unroll 1
-    for (int pass = 0; pass < G::PASSES; ++pass) {
-        L acc[G::WP][NQ];
+        for (int pass = 0; pass < G::PASSES; ++pass) {
+            L acc[G::WP][NQ];
 #pragma unroll
-        for (int s = 0; s < G::WP; ++s)
+            for (int s = 0; s < G::WP; ++s)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[s][q] = (L)0;
+                for (int q = 0; q < NQ; ++q) acc[s][q] = acc_zero<PREC>();
 
-        // a particle whose scalars the first pass cached loads only X again
-        auto need = [&](int f, uint32_t kk) { return !(pass > 0 && f >= DIM && kk - beg < FJ); };
-        R cur[NPF];
+            // a particle whose scalars the first pass cached loads only X again
+            auto need = [&](int f, uint32_t kk) { return !(pass > 0 && f >= DIM && kk - beg < FJ); };
+            R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
+            for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
-        for (uint32_t k = beg; k < end; ++k) {
-            R nxt[NPF];
-            const uint32_t kn = min(k + 1, end - 1);
+            for (uint32_t k = beg; k < end; ++k) {
+                R nxt[NPF];
+                const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
-            R x[3] = {0, 0, 0};
-            S1In<R> in;
-            in.v[0] = in.v[1] = in.v[2] = 0;
+                for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
+                R x[3] = {0, 0, 0};
+                S1In<R> in;
+                in.v[0] = in.v[1] = in.v[2] = 0;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                x[a] = cur[a];
-                in.v[a] = cur[DIM + a];
-            }
-            in.D = cur[2 * DIM + 3];
-            in.M = cur[2 * DIM];
-            in.rho = cur[2 * DIM + 1];
-            in.e = cur[2 * DIM + 2];
-            Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(&V, x, st);
-            // A particle whose cell changed between sort and use adds zeros
-            // here (no divergence in the register sums) and is summed by the
-            // deferred loop below (rare).
-            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (pass == 0) mismatch += own ? 0u : 1u;
-            // the particle's scalars: computed, or in 3D cached by the first
-            // pass for the other two
-            R sc[5];
-            const uint32_t kj = k - beg;
-            if (pass > 0 && kj < FJ) {
-#pragma unroll
-                for (int i = 0; i < 5; ++i) sc[i] = fcache[(i * FJ + kj) * kBlock + threadIdx.x];
-            } else {
-                s1_scalars<DIM, PREC>(&V, in, sc, own);
-                if (kj < FJ)
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) fcache[(i * FJ + kj) * kBlock + threadIdx.x] = sc[i];
-            }
-            S1Factors<DIM, SHAPE, R> f;
-            s1_products<DIM, SHAPE, R>(sc, st, f);
-            const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
-            const R dwz = DIM == 3 ? pick<W, R>(st.dw[2], pass) : (R)0;
-            const double bias = term_bias(k - beg);
-#pragma unroll
-            for (int jy = 0; jy < W; ++jy) {
-                const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
-                const R dyz = DIM == 3 ? st.dw[1][jy] * wz : st.dw[1][jy];
-                const R ydz = st.w[1][jy] * dwz;
-#pragma unroll
-                for (int jx = 0; jx < W; ++jx) {
-                    L *ac = acc[jy * W + jx];
-                    ac[0] += term<PREC>(f.mx[jx], wyz, bias);
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) ac[1 + a] += term<PREC>(f.px[a][jx], wyz, bias);
-                    ac[1 + DIM] += term<PREC>(f.fx[jx], wyz, bias);
-                    ac[2 + DIM] += term<PREC>(f.gx[jx], dyz, bias);
-                    if constexpr (DIM == 3) ac[3 + DIM] += term<PREC>(f.gx[jx], ydz, bias);
+                for (int a = 0; a < DIM; ++a) {
+                    x[a] = cur[a];
+                    in.v[a] = cur[DIM + a];
                 }
-            }
+                in.D = cur[2 * DIM + 3];
+                in.M = cur[2 * DIM];
+                in.rho = cur[2 * DIM + 1];
+                in.e = cur[2 * DIM + 2];
+                Stencil<DIM, SHAPE, R> st;
+                make_stencil<DIM, SHAPE, R, EDGE>(&V, x, st);
+                // A particle whose cell changed between sort and use adds zeros
+                // here (no divergence in the register sums) and is summed by the
+                // deferred loop below (rare).
+                const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+                if (pass == 0) mismatch += own ? 0u : 1u;
+                // the particle's scalars: computed, or in 3D cached by the first
+                // pass for the other two
+                R sc[5];
+                const uint32_t kj = k - beg;
+                if (pass > 0 && kj < FJ) {
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
-        }
-        if (end > beg) {
-            const int lz = DIM == 3 ? lc[2] + pass : 0;
+                    for (int i = 0; i < 5; ++i) sc[i] = fcache[(i * FJ + kj) * kBlock + threadIdx.x];
+                } else {
+                    s1_scalars<DIM, PREC>(&V, in, sc, own);
+                    if (kj < FJ)
 #pragma unroll
-            for (int jy = 0; jy < W; ++jy)
+                        for (int i = 0; i < 5; ++i) fcache[(i * FJ + kj) * kBlock + threadIdx.x] = sc[i];
+                }
+                S1Factors<DIM, SHAPE, R> f;
+                s1_products<DIM, SHAPE, R>(sc, st, f);
+                const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
+                const R dwz = DIM == 3 ? pick<W, R>(st.dw[2], pass) : (R)0;
 #pragma unroll
-                for (int jx = 0; jx < W; ++jx) {
-                    const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
+                for (int jy = 0; jy < W; ++jy) {
+                    const auto wyz = weight<PREC>(DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy]);
+                    const auto dyz = weight<PREC>(DIM == 3 ? st.dw[1][jy] * wz : st.dw[1][jy]);
+                    const auto ydz = weight<PREC>(st.w[1][jy] * dwz);
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        const L v = unbias<PREC>(acc[jy * W + jx][q], end - beg);
-                        if (v != (L)0) lds_add(&tile[q * G::TN + li], v);
+                    for (int jx = 0; jx < W; ++jx) {
+                        L *ac = acc[jy * W + jx];
+                        ac[0] = accum<PREC>(ac[0], f.mx[jx], wyz);
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) ac[1 + a] = accum<PREC>(ac[1 + a], f.px[a][jx], wyz);
+                        ac[1 + DIM] = accum<PREC>(ac[1 + DIM], f.fx[jx], wyz);
+                        ac[2 + DIM] = accum<PREC>(ac[2 + DIM], f.gx[jx], dyz);
+                        if constexpr (DIM == 3) ac[3 + DIM] = accum<PREC>(ac[3 + DIM], f.gx[jx], ydz);
                     }
                 }
+#pragma unroll
+                for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
+            }
+            if (end > beg) {
+                const int lz = DIM == 3 ? lc[2] + pass : 0;
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx) {
+                        const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            const L v = unbias<PREC>(acc[jy * W + jx][q]);
+                            if (v != (L)0) lds_add(&tile[q * G::TN + li], v);
+                        }
+                    }
+            }
         }
-    }
+    };
+    if (interior) sweep(std::false_type{});
+    else sweep(std::true_type{});
     if (mismatch) {
         // Particles whose cell changed between sort and use: their
         // contributions go one by one into the LDS tile (their cell must
@@ -637,6 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     GLOBAL_AS uint32_t *const cnt_g = gmem(P->count), *const ttot_g = gmem(P->ttot);
     int c0[3], lc0[3];
     tile_cell<DIM>(P, t, c0, lc0);
+    const bool interior = tile_interior<DIM, SHAPE>(V, c0);
     uint32_t flags = 0;
 
     for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (L)0;
@@ -673,104 +695,110 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     };
     // Each lane walks the particles of its cell, loading the next
     // particle's fields while the current one is processed.
+    // (compiled once for interior tiles, uniform B2 pieces only, and once
+    // for tiles at a domain face)
+    auto sweep = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
 #pragma unroll 1
-    for (int pass = 0; pass < (kP2G ? G::PASSES : 1); ++pass) {
-        L acc[G::WP][DIM];
+        for (int pass = 0; pass < (kP2G ? G::PASSES : 1); ++pass) {
+            L acc[G::WP][DIM];
 #pragma unroll
-        for (int s = 0; s < G::WP; ++s)
+            for (int s = 0; s < G::WP; ++s)
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) acc[s][a] = (L)0;
+                for (int a = 0; a < DIM; ++a) acc[s][a] = acc_zero<PREC>();
 
-        // V of a particle whose V' the first pass cached is not loaded again
-        auto need = [&](int f, uint32_t kk) {
-            return !(pass > 0 && f >= DIM && f < 2 * DIM && kk - beg < VJ);
-        };
-        R cur[NPF];
+            // V of a particle whose V' the first pass cached is not loaded again
+            auto need = [&](int f, uint32_t kk) {
+                return !(pass > 0 && f >= DIM && f < 2 * DIM && kk - beg < VJ);
+            };
+            R cur[NPF];
 #pragma unroll
-        for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
+            for (int f = 0; f < NPF; ++f) cur[f] = end > beg && need(f, beg) ? ldk(src[f], beg) : (R)0;
 #pragma unroll 1
-        for (uint32_t k = beg; k < end; ++k) {
-            R nxt[NPF];
-            const uint32_t kn = min(k + 1, end - 1);
+            for (uint32_t k = beg; k < end; ++k) {
+                R nxt[NPF];
+                const uint32_t kn = min(k + 1, end - 1);
 #pragma unroll
-            for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
-            R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+                for (int f = 0; f < NPF; ++f) nxt[f] = need(f, kn) ? ldk(src[f], kn) : (R)0;
+                R x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                x[a] = cur[a];
-                v[a] = cur[DIM + a];
-            }
-            Stencil<DIM, SHAPE, R> st;
-            make_stencil<DIM, SHAPE, R>(&V, x, st);
-            // A particle whose cell changed between sort and use adds zeros
-            // here and is handled by the deferred loop below (rare).
-            const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
-            if (pass == 0) mismatch += own ? 0u : 1u;
-            // G2P of the velocity increment, row by row: V' = V + dv.  V'
-            // is not stored (the update sweep recomputes it from the same
-            // staged values, same bits).  In 3D the first pass keeps it in
-            // LDS for the other two.
-            const uint32_t kj = k - beg;
-            if (!kP2G) {
-                // V' is not needed here
-            } else if (pass > 0 && kj < VJ) {
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) v[a] = vcache[(a * VJ + kj) * kBlock + threadIdx.x];
-            } else {
-                R dv[3];
-                g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, lc, dv);
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
-                if (kj < VJ)
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) vcache[(a * VJ + kj) * kBlock + threadIdx.x] = v[a];
-            }
-            if (pass == 0 && own) {
-                // G2P of vstar: the move, the new cell key and the rank
-                R vbar[3];
-                g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
-                uint32_t nk, rk;
-                s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
-                put_rank(k, rk);
-            }
-            if constexpr (kP2G) {
-            const R Ms = own ? cur[2 * DIM] * sp : (R)0;
-            R px[3][W];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                const R mv = own ? Ms * v[a] : (R)0;
-#pragma unroll
-                for (int j = 0; j < W; ++j) px[a][j] = mv * st.w[0][j];
-            }
-            const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
-            const double bias = term_bias(k - beg);
-#pragma unroll
-            for (int jy = 0; jy < W; ++jy) {
-                const R wyz = DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy];
-#pragma unroll
-                for (int jx = 0; jx < W; ++jx)
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] += term<PREC>(px[a][jx], wyz, bias);
-            }
-            }
-#pragma unroll
-            for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
-        }
-        if (kP2G && end > beg) {
-            const int lz = DIM == 3 ? lc[2] + pass : 0;
-#pragma unroll
-            for (int jy = 0; jy < W; ++jy)
-#pragma unroll
-                for (int jx = 0; jx < W; ++jx) {
-                    const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        const L v = unbias<PREC>(acc[jy * W + jx][a], end - beg);
-                        if (v != (L)0) lds_add(&tile[a * G::TN + li], v);
-                    }
+                for (int a = 0; a < DIM; ++a) {
+                    x[a] = cur[a];
+                    v[a] = cur[DIM + a];
                 }
+                Stencil<DIM, SHAPE, R> st;
+                make_stencil<DIM, SHAPE, R, EDGE>(&V, x, st);
+                // A particle whose cell changed between sort and use adds zeros
+                // here and is handled by the deferred loop below (rare).
+                const bool own = st.c[0] == cell[0] && st.c[1] == cell[1] && (DIM == 2 || st.c[2] == cell[2]);
+                if (pass == 0) mismatch += own ? 0u : 1u;
+                // G2P of the velocity increment, row by row: V' = V + dv.  V'
+                // is not stored (the update sweep recomputes it from the same
+                // staged values, same bits).  In 3D the first pass keeps it in
+                // LDS for the other two.
+                const uint32_t kj = k - beg;
+                if (!kP2G) {
+                    // V' is not needed here
+                } else if (pass > 0 && kj < VJ) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) v[a] = vcache[(a * VJ + kj) * kBlock + threadIdx.x];
+                } else {
+                    R dv[3];
+                    g2p_field<DIM, SHAPE, R, NF, DIM>(stage, st, lc, dv);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) v[a] = v[a] + dv[a];
+                    if (kj < VJ)
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) vcache[(a * VJ + kj) * kBlock + threadIdx.x] = v[a];
+                }
+                if (pass == 0 && own) {
+                    // G2P of vstar: the move, the new cell key and the rank
+                    R vbar[3];
+                    g2p_field<DIM, SHAPE, R, NF, 0>(stage, st, lc, vbar);
+                    uint32_t nk, rk;
+                    s2_key_rank<DIM, R>(&V, cnt_g, ttot_g, x, vbar, dt, IdAt{idg, k}, c0, hist, nk, rk, flags);
+                    put_rank(k, rk);
+                }
+                if constexpr (kP2G) {
+                const R Ms = own ? cur[2 * DIM] * sp : (R)0;
+                R px[3][W];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const R mv = own ? Ms * v[a] : (R)0;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) px[a][j] = mv * st.w[0][j];
+                }
+                const R wz = DIM == 3 ? pick<W, R>(st.w[2], pass) : (R)1;
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy) {
+                    const auto wyz = weight<PREC>(DIM == 3 ? st.w[1][jy] * wz : st.w[1][jy]);
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx)
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) acc[jy * W + jx][a] = accum<PREC>(acc[jy * W + jx][a], px[a][jx], wyz);
+                }
+                }
+#pragma unroll
+                for (int f = 0; f < NPF; ++f) cur[f] = nxt[f];
+            }
+            if (kP2G && end > beg) {
+                const int lz = DIM == 3 ? lc[2] + pass : 0;
+#pragma unroll
+                for (int jy = 0; jy < W; ++jy)
+#pragma unroll
+                    for (int jx = 0; jx < W; ++jx) {
+                        const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            const L v = unbias<PREC>(acc[jy * W + jx][a]);
+                            if (v != (L)0) lds_add(&tile[a * G::TN + li], v);
+                        }
+                    }
+            }
         }
-    }
+    };
+    if (interior) sweep(std::false_type{});
+    else sweep(std::true_type{});
     if (mismatch) {
         // Particles whose cell changed between sort and use: G2P from the
         // global grid, P2G into the LDS tile (their cell must still lie in
@@ -1629,6 +1657,7 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
     const View V = make_view(P);
     int c0[3], lc[3];
     tile_cell<DIM>(P, t, c0, lc);
+    const bool interior = tile_interior<DIM, SHAPE>(V, c0);
     uint32_t flags = 0;
     stage_tile<DIM, SHAPE, PREC, true>(P, t, c0, stage, flags);
     // Per destination footprint cell: its offset in the next order plus
@@ -1652,17 +1681,24 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
     const uint32_t pbeg = off[(uint32_t)t * G::CELLS], pend = off[(uint32_t)(t + 1) * G::CELLS];
     S3Sums sums = {0, 0, 0, {0, 0, 0}, 0, 0, 0, 0, 0};
 
+    // (compiled once for interior tiles, uniform B2 pieces only, and once
+    // for tiles at a domain face)
+    auto sweep = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
 #pragma unroll 1
-    for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
-        const S3In<R> in = s3_load<DIM, R>(src, k);     // every input in one round trip
-        Stencil<DIM, SHAPE, R> st;
-        make_stencil<DIM, SHAPE, R>(&V, in.x, st);
-        const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
-        const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
-                            (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
-        if (!inside) { ++sums.mis; continue; }       // handled below (rare)
-        s3_particle<DIM, SHAPE, PREC, false>(P, &V, dst, in, st, l0, stage, sfoot, sums, flags);
-    }
+        for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
+            const S3In<R> in = s3_load<DIM, R>(src, k);     // every input in one round trip
+            Stencil<DIM, SHAPE, R> st;
+            make_stencil<DIM, SHAPE, R, EDGE>(&V, in.x, st);
+            const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
+            const bool inside = l0[0] >= 0 && l0[0] < G::TX && l0[1] >= 0 && l0[1] < G::TY &&
+                                (DIM == 2 || (l0[2] >= 0 && l0[2] < G::TZ));
+            if (!inside) { ++sums.mis; continue; }       // handled below (rare)
+            s3_particle<DIM, SHAPE, PREC, false>(P, &V, dst, in, st, l0, stage, sfoot, sums, flags);
+        }
+    };
+    if (interior) sweep(std::false_type{});
+    else sweep(std::true_type{});
     if (sums.mis) {
 #pragma unroll 1
         for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
