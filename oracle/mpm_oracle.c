@@ -15,6 +15,11 @@
  * block of ids into its own node arrays, and those are added in thread
  * order, so the result differs from one thread by FP64 rounding only.  Used
  * to time the CPU baseline on all host cores and to shorten long runs.
+ *
+ * FP32 state (orc_set_fp32_state; off by default): the particle state is
+ * rounded to FP32 at the call and after every step, the arithmetic staying
+ * FP64.  It measures what storing the state in FP32 alone does to a long
+ * run, the floor an FP32-state implementation is compared against.
  */
 #include "oracle.h"
 
@@ -44,6 +49,7 @@ struct orc_state {
     int64_t wall_escapes;
     int failed;
     int nthreads;          /* OpenMP threads of the loops (1: sequential)   */
+    int fp32_state;        /* round the particle state to FP32 after a step  */
     double *priv;          /* nthreads * (1 + 2 dim) node arrays (P2G sums) */
 };
 
@@ -455,6 +461,31 @@ int orc_set_threads(orc_state *s, int n) {
     return ORC_OK;
 }
 
+/* Round every stored particle field (X, V, M, rho, E, G) to FP32. */
+static void round_state_fp32(orc_state *s) {
+    const int dim = s->pb.dim;
+    const int nt = s->nthreads;
+    (void)nt;
+#pragma omp parallel for num_threads(nt) if (nt > 1)
+    for (int64_t k = 0; k < s->np; ++k) {
+        for (int a = 0; a < dim; ++a) {
+            s->x[a][k] = (double)(float)s->x[a][k];
+            s->v[a][k] = (double)(float)s->v[a][k];
+        }
+        s->M[k] = (double)(float)s->M[k];
+        s->rho[k] = (double)(float)s->rho[k];
+        s->E[k] = (double)(float)s->E[k];
+        for (int i = 0; i < dim * dim; ++i) s->G[i][k] = (double)(float)s->G[i][k];
+    }
+}
+
+int orc_set_fp32_state(orc_state *s, int on) {
+    if (!s) return ORC_E_ARG;
+    s->fp32_state = on != 0;
+    if (s->fp32_state) round_state_fp32(s);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------- one step -- */
 
 /* Nodal value u/m, zero where the node carries no mass (reading: nodes with
@@ -719,6 +750,7 @@ int orc_step(orc_state *s, int64_t n_steps) {
         while (s->t < s->pb.t_end && s->dt > 0.0) {
             int rc = one_step(s);
             if (rc) return rc;
+            if (s->fp32_state) round_state_fp32(s);
         }
         return ORC_OK;
     }
@@ -727,6 +759,7 @@ int orc_step(orc_state *s, int64_t n_steps) {
         if (!(s->dt > 0.0)) break;
         int rc = one_step(s);
         if (rc) return rc;
+        if (s->fp32_state) round_state_fp32(s);
     }
     return ORC_OK;
 }

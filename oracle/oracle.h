@@ -85,6 +85,11 @@ int orc_set_dt(orc_state *s, double dt);
  * n > 1 in a build without OpenMP. */
 int orc_set_threads(orc_state *s, int n);
 
+/* FP32 state: on != 0 rounds the particle fields (X, V, M, rho, E, G) to
+ * FP32 now and after every step; the arithmetic stays FP64.  Test support:
+ * the effect of FP32 storage alone on a long run. */
+int orc_set_fp32_state(orc_state *s, int on);
+
 /* Read-out of the grid-projected density: mass[i] = sum_k M_k phi_i(X_k)
  * and vol[i] = sum_k (M_k / rho_k) phi_i(X_k) at the current positions (two
  * arrays over the node grid, x fastest); the projected density is

@@ -68,6 +68,7 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_set_dt.argtypes = [C.c_void_p, C.c_double]
         L.orc_set_threads.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_fp32_state.argtypes = [C.c_void_p, C.c_int]
         L.orc_projected.argtypes = [C.c_void_p, dp, dp]
         L.orc_get_particles.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_get_grid.argtypes = [C.c_void_p, C.c_int, dp]
@@ -182,6 +183,13 @@ class Oracle:
 
     def step(self, n: int = 1) -> int:
         return lib().orc_step(self._h, int(n))
+
+    def set_fp32_state(self, on: bool = True):
+        """Round the particle state to FP32 now and after every step (the
+        arithmetic stays FP64): the effect of FP32 storage alone."""
+        rc = lib().orc_set_fp32_state(self._h, int(bool(on)))
+        if rc:
+            raise OracleError(rc, "orc_set_fp32_state")
 
     def set_dt(self, dt: float):
         rc = lib().orc_set_dt(self._h, float(dt))

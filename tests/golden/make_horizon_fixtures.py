@@ -12,16 +12,21 @@ For each: the oracle runs the workload's steps (all host cores; the P2G sums
 then differ from one thread by FP64 rounding) and reaches the time t.  A
 second oracle whose initial positions are scaled by (1 + 1e-7 u),
 u ~ U(-1, 1) seeded -- a perturbation the size of FP32 rounding -- runs to
-that same time t (its time steps, a maximum over the particles, differ).
+that same time t (its time steps, a maximum over the particles, differ).  A
+third oracle rounds its particle state to FP32 after every step (FP64
+arithmetic, FP32 storage) and runs to t as well: the floor of an FP32-state
+implementation, which carries a rounding of that size at every step rather
+than once.
 The grid-projected density (sum M phi / sum (M / rho) phi at the final
 positions) is averaged over blocks of 16 x 16 nodes (block mass over block
 volume); the fixture holds the oracle's block densities, t, and the relative
-L1 between the two oracle runs, per block and per particle (the floor).
+L1 of the block densities of the perturbed and of the FP32-state run against
+them (the two floors).
 
 Only oracle/ and the input generator are used.  Run from the repository
 root: python tests/golden/make_horizon_fixtures.py [name ...]; a fixture
-that already holds a reference run of the same steps keeps it and only the
-perturbed run is redone.
+that already holds a reference run of the same steps keeps it, and a floor
+it already holds is kept.
 """
 import json
 import os
@@ -63,9 +68,11 @@ def rel_l1(a, b):
     return float(np.abs(a[ok] - b[ok]).sum() / np.abs(b[ok]).sum())
 
 
-def run(pb, steps, threads):
+def run(pb, steps, threads, fp32_state=False):
     """steps > 0: that many steps; steps = 0: to pb.t_end."""
     o = O.Oracle(pb, threads=threads)
+    if fp32_state:
+        o.set_fp32_state(True)
     t0 = time.time()
     rc = o.step(steps)
     assert rc == 0, rc
@@ -96,22 +103,37 @@ def main(names):
             with open(out, "w") as f:
                 json.dump(rec, f, separators=(",", ":"))
             print(f"{name}: oracle {steps} steps in {sec:.0f} s, t = {st['t']:.6f}", flush=True)
-        rng = np.random.default_rng(2404)
-        pb.x = pb.x * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0, size=pb.x.shape))
-        pb.x = np.minimum(pb.x, np.array(pb.hi[:2])[:, None] * (1 - 1e-12))
-        pb.t_end = rec["t"]
-        blocks_p, rho_p, st_p, sec = run(pb, 0, threads)
-        print(f"{name}: perturbed oracle to t in {sec:.0f} s, {st_p['step']} steps", flush=True)
-        rec.update({
-            "floor_rel_l1_blocks": rel_l1(blocks_p, blocks),
-            "perturbed_steps": st_p["step"],
-            "perturbation": "initial positions scaled by 1 + 1e-7 U(-1,1), seed 2404; run to the same t",
-        })
-        if rho is not None:
-            rec["floor_rel_l1_particles"] = float(np.abs(rho_p - rho).sum() / np.abs(rho).sum())
-        with open(out, "w") as f:
-            json.dump(rec, f, separators=(",", ":"))
-        print(f"{name}: floor blocks {rec['floor_rel_l1_blocks']:.3e} -> {out}", flush=True)
+        if "floor_rel_l1_blocks" not in rec:
+            pp = make()
+            rng = np.random.default_rng(2404)
+            pp.x = pp.x * (1.0 + 1e-7 * rng.uniform(-1.0, 1.0, size=pp.x.shape))
+            pp.x = np.minimum(pp.x, np.array(pp.hi[:2])[:, None] * (1 - 1e-12))
+            pp.t_end = rec["t"]
+            blocks_p, rho_p, st_p, sec = run(pp, 0, threads)
+            print(f"{name}: perturbed oracle to t in {sec:.0f} s, {st_p['step']} steps", flush=True)
+            rec.update({
+                "floor_rel_l1_blocks": rel_l1(blocks_p, blocks),
+                "perturbed_steps": st_p["step"],
+                "perturbation": "initial positions scaled by 1 + 1e-7 U(-1,1), seed 2404; run to the same t",
+            })
+            if rho is not None:
+                rec["floor_rel_l1_particles"] = float(np.abs(rho_p - rho).sum() / np.abs(rho).sum())
+            with open(out, "w") as f:
+                json.dump(rec, f, separators=(",", ":"))
+            print(f"{name}: floor blocks {rec['floor_rel_l1_blocks']:.3e} -> {out}", flush=True)
+        if "floor_fp32_state_rel_l1_blocks" not in rec:
+            pf = make()
+            pf.t_end = rec["t"]
+            blocks_f, _, st_f, sec = run(pf, 0, threads, fp32_state=True)
+            print(f"{name}: FP32-state oracle to t in {sec:.0f} s, {st_f['step']} steps", flush=True)
+            rec.update({
+                "floor_fp32_state_rel_l1_blocks": rel_l1(blocks_f, blocks),
+                "fp32_state_steps": st_f["step"],
+            })
+            with open(out, "w") as f:
+                json.dump(rec, f, separators=(",", ":"))
+            print(f"{name}: FP32-state floor blocks {rec['floor_fp32_state_rel_l1_blocks']:.3e} -> {out}",
+                  flush=True)
 
 
 if __name__ == "__main__":

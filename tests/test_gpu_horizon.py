@@ -6,14 +6,16 @@ The flow is chaotic at these horizons: outflow recycling makes discrete
 choices, and the time step is a maximum over the particles, so after the
 workload's steps two runs differing by rounding have reached different
 times.  The comparison is at equal time: the fixture holds the time t the
-oracle reaches in the workload's steps, and the GPU runs to that t.  A
-perturbation the size of FP32 rounding (initial positions scaled by
-1 + 1e-7 u) moves the oracle's own result at t by the floor stored in the
-fixture (tests/golden/horizon_*.json, written by
-tests/golden/make_horizon_fixtures.py from the oracle alone).  A GPU result
-whose distance to the oracle is within twice that floor cannot be told
-apart from the oracle at this horizon; that is the bar, for the FP32
-fixed-point path and for the FP64 path.
+oracle reaches in the workload's steps, and the GPU runs to that t.  Two
+floors come with it (tests/golden/horizon_*.json, written by
+tests/golden/make_horizon_fixtures.py from the oracle alone): a perturbation
+the size of FP32 rounding once, at the start (initial positions scaled by
+1 + 1e-7 u), moves the oracle's result at t by the first; rounding the
+oracle's particle state to FP32 after every step, as an FP32-state code
+stores it, moves it by the second.  A GPU result whose distance to the
+oracle is within twice the floor of what it carries cannot be told apart
+from the oracle at this horizon; that is the bar: the first floor for the
+FP64 path, the larger of the two for the FP32-state fixed-point path.
 """
 import json
 import os
@@ -61,6 +63,11 @@ def test_full_horizon_projected_density(name, prec):
     fx = json.load(open(path))
     if "floor_rel_l1_blocks" not in fx:
         pytest.skip(f"{path} holds no floor yet")
+    floor = fx["floor_rel_l1_blocks"]
+    if prec != G.FP64:
+        if "floor_fp32_state_rel_l1_blocks" not in fx:
+            pytest.skip(f"{path} holds no FP32-state floor yet")
+        floor = max(floor, fx["floor_fp32_state_rel_l1_blocks"])
     ref = np.array([np.nan if v is None else v for v in fx["density_blocks"]]).reshape(fx["shape"])
     pb = MAKE[name]()
     pb.t_end = fx["t"]
@@ -68,13 +75,13 @@ def test_full_horizon_projected_density(name, prec):
     s = G.Simulation(pb, prec)
     s.step(0)
     st = s.status()
+    # the step count to reach t is not compared: the time step follows the
+    # fastest particle, whose FLIP velocity noise differs from run to run
+    # (the perturbed oracle takes far more steps to the same t)
     assert st["rc"] == 0 and st["t"] == fx["t"]
-    # the step count differs from the oracle's by the chaos of the time step
-    assert abs(st["step"] - fx["steps"]) <= 0.05 * fx["steps"]
     got = block_density(s.grid(G.G_MPROJ), s.grid(G.G_VOLPROJ), s.nodes, fx["block_nodes"])
     ok = np.isfinite(got) & np.isfinite(ref)
     assert np.array_equal(np.isfinite(got), np.isfinite(ref))
     l1 = float(np.abs(got[ok] - ref[ok]).sum() / np.abs(ref[ok]).sum())
-    floor = fx["floor_rel_l1_blocks"]
     print(f"  rel L1 of the block density vs oracle {l1:.3e}, floor {floor:.3e}, steps {st['step']}", flush=True)
     assert l1 <= 2.0 * floor
