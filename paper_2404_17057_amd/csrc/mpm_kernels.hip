@@ -399,8 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
                         const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
                         for (int q = 0; q < NQ; ++q) {
-                            const L v = unbias<PREC>(acc[jy * W + jx][q]);
-                            if (v != (L)0) lds_add(&tile[q * G::TN + li], v);
+                            // zeros are added too: a test per value costs more
+                            // than the LDS atomic it saves (2D S1 52.3 -> 49.9
+                            // us, 3D S1 6.59 -> 6.45 ms)
+                            lds_add(&tile[q * G::TN + li], unbias<PREC>(acc[jy * W + jx][q]));
                         }
                     }
             }
@@ -790,8 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
                         const int li = (lz * G::NY + (lc[1] + jy)) * G::NX + (lc[0] + jx);
 #pragma unroll
                         for (int a = 0; a < DIM; ++a) {
-                            const L v = unbias<PREC>(acc[jy * W + jx][a]);
-                            if (v != (L)0) lds_add(&tile[a * G::TN + li], v);
+                            lds_add(&tile[a * G::TN + li], unbias<PREC>(acc[jy * W + jx][a]));
                         }
                     }
             }
