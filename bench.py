@@ -231,7 +231,7 @@ def ablation(args):
     out = {"workload": f"cylinder_mach3_512x256_ppc16 ({pb.n_particles} particles)",
            "steps": args.ablation_steps, "oracle_steps": args.ablation_oracle_steps, "modes": {}}
     for name, prec in (("fp32_acc_f64", G.FP32_ACC_F64), ("fp32_acc_f32", G.FP32_ACC_F32),
-                       ("fp32_fix64", G.FP32_FIX64), ("fp64", G.FP64)):
+                       ("fp32_fix64", G.FP32_FIX64), ("fp64", G.FP64), ("fp64_colouring", G.FP64_COLOR)):
         rec = {}
         s = G.Simulation(pb, prec)
         s.step(args.ablation_oracle_steps)
@@ -249,7 +249,7 @@ def ablation(args):
                 s.step(k)
                 done += k
                 if run == 0:
-                    M0 = M0s["fp64" if prec == G.FP64 else "fp32"]
+                    M0 = M0s["fp64" if prec in (G.FP64, G.FP64_COLOR) else "fp32"]
                     drift = max(drift, abs(float(s.grid(G.G_M).sum()) - M0) / M0)
             if run == 1:
                 torch_sync()
