@@ -460,7 +460,7 @@ template <int DIM, bool WITH_B> constexpr int stage_stride() { return (WITH_B ? 
 // Stage the tile footprint of nodes, interleaved per node:
 // lds[li * NF + f]: f < DIM vstar, DIM <= f < 2 DIM dvel, 2 DIM <= f v2 (S3).
 template <int DIM, int SHAPE, int PREC, bool WITH_B>
-__device__ __forceinline__ void stage_tile(const ProbDev *P, int t, const int c0[3],
+__device__ __forceinline__ void stage_tile(const ProbDev *P, const int c0[3],
                                            typename PrecT<PREC>::real *lds, uint32_t &flags) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
@@ -499,9 +499,10 @@ __device__ __forceinline__ const R *node_ptr(const R *lds, const int l0[3], int 
 template <int DIM, int SHAPE, typename R, int NF, int OFF, bool ROLLED = false>
 __device__ __forceinline__ void g2p_field(const R *lds, const Stencil<DIM, SHAPE, R> &st, const int l0[3], R out[3]) {
     constexpr int W = Geo<DIM, SHAPE>::W;
+    constexpr int kZUnroll = ROLLED ? 1 : 3;
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = 0;
-#pragma unroll (ROLLED ? 1 : 3)
+#pragma unroll kZUnroll
     for (int jz = 0; jz < (DIM == 3 ? W : 1); ++jz)
 #pragma unroll
         for (int jy = 0; jy < W; ++jy) {
@@ -625,7 +626,6 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     using G = Geo<DIM, SHAPE>;
     using R = typename PrecT<PREC>::real;
     using L = typename PrecT<PREC>::lacc;
-    using A = typename PrecT<PREC>::acc;
     constexpr int W = G::W;
     constexpr int NF = stage_stride<DIM, false>();
     constexpr int ND = DestFoot<DIM>::N;
@@ -665,7 +665,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
 
     for (int i = threadIdx.x; i < DIM * G::TN; i += kBlock) tile[i] = (L)0;
     for (int i = threadIdx.x; i < ND; i += kBlock) hist[i] = 0;
-    stage_tile<DIM, SHAPE, PREC, false>(P, t, c0, stage, flags);
+    stage_tile<DIM, SHAPE, PREC, false>(P, c0, stage, flags);
     __syncthreads();
 
     const bool valid = c0[0] + lc0[0] < P->n[0] && c0[1] + lc0[1] < P->n[1] &&
@@ -1660,7 +1660,7 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
     tile_cell<DIM>(P, t, c0, lc);
     const bool interior = tile_interior<DIM, SHAPE>(V, c0);
     uint32_t flags = 0;
-    stage_tile<DIM, SHAPE, PREC, true>(P, t, c0, stage, flags);
+    stage_tile<DIM, SHAPE, PREC, true>(P, c0, stage, flags);
     // Per destination footprint cell: its offset in the next order plus
     // this tile's base among the cell's particles (only cells that receive
     // particles from this tile are read).
@@ -1888,8 +1888,6 @@ __global__ __launch_bounds__(kBlock) void k_project(const ProbDev *P, int which,
 }
 
 // ------------------------------------------------------------- launchers --
-static inline dim3 grid1(int n) { return dim3((unsigned)n); }
-
 // One sweep of the step (part 0..5 in launch order).
 template <int DIM, int SHAPE, int PREC>
 void launch_part_t(int part, const WorkTab &tiles, const WorkTab &single, hipStream_t s) {
