@@ -167,6 +167,8 @@ Layout make_layout(const mpm_desc *d) {
     L.acc_sz = d->precision == MPM_FP32_ACC_F32 ? 4 : 8;
     size_t o = 0;
     L.off_prob = o; o = align_up(o + sizeof(ProbDev));
+    // Fields of one parity follow each other at one stride (the update sweep
+    // addresses the G components as component 0 plus c strides).
     for (int p = 0; p < 2; ++p) {
         for (int f = 0; f < PF_N; ++f) {
             L.off_part[p][f] = (size_t)-1;

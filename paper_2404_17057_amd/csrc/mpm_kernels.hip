@@ -1425,7 +1425,11 @@ template <int DIM, typename R> struct S3Src {
 
 // Destination arrays of S3 (the next parity) and the next cell offsets.
 template <int DIM, typename R> struct S3Dst {
-    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d, *g[9];
+    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d;
+    // G: component c (row-major) at g0 + c * gs (the components are
+    // consecutive particle fields of one size in the workspace)
+    GLOBAL_AS R *g0;
+    long long gs;
     GLOBAL_AS uint32_t *id;
     const GLOBAL_AS uint32_t *noff;
     bool full_g;              // the last step of the run: write the whole G too
@@ -1580,8 +1584,15 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
     // the next step would form from the stored diagonal, the same bits
     stk(dst.d, slot, mv == 1 ? (R)0 : D);
     if (dst.full_g) {
+        // The empty asm makes base and stride new values here, so the nine
+        // component addresses are formed in this branch: hoisted out of the
+        // particle loop they were 18 more live scalar registers, which spilled
+        // and were reloaded for every particle.
+        GLOBAL_AS R *g0 = dst.g0;
+        long long gs = dst.gs;
+        asm volatile("" : "+s"(g0), "+s"(gs));
 #pragma unroll
-        for (int c = 0; c < DIM * DIM; ++c) stk(dst.g[c], slot, Gm[c]);
+        for (int c = 0; c < DIM * DIM; ++c) stk(g0 + c * gs, slot, Gm[c]);
     }
     stk(dst.id, slot, id);
 
@@ -1645,8 +1656,8 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
             dst.x[a] = gmem((R *)P->part[np1][PF_X + aa]);
             dst.v[a] = gmem((R *)P->part[np1][PF_V + aa]);
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) dst.g[c] = gmem((R *)P->part[np1][PF_G + (c < DIM * DIM ? c : 0)]);
+        dst.g0 = gmem((R *)P->part[np1][PF_G]);
+        dst.gs = ((const char *)P->part[np1][PF_G + 1] - (const char *)P->part[np1][PF_G]) / (long long)sizeof(R);
         dst.M = gmem((R *)P->part[np1][PF_M]);
         dst.rho = gmem((R *)P->part[np1][PF_RHO]);
         dst.e = gmem((R *)P->part[np1][PF_E]);
@@ -1689,9 +1700,22 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
     // for tiles at a domain face)
     auto sweep = [&](auto edge_tag) {
         constexpr bool EDGE = decltype(edge_tag)::value;
+        // 3D: the lane's next particle is loaded while this one is updated
+        // (the index clamped to the tile's last particle).  2D S3, held at
+        // 128 registers, would spill the extra inputs.
+        constexpr bool AHEAD = DIM == 3;
+        uint32_t k = pbeg + threadIdx.x;
+        S3In<R> nxt{};
+        if (AHEAD && pbeg < pend) nxt = s3_load<DIM, R>(src, min(k, pend - 1));
 #pragma unroll 1
-        for (uint32_t k = pbeg + threadIdx.x; k < pend; k += kBlock) {
-            const S3In<R> in = s3_load<DIM, R>(src, k);     // every input in one round trip
+        for (; k < pend; k += kBlock) {
+            S3In<R> in;                                      // every input in one round trip
+            if constexpr (AHEAD) {
+                in = nxt;
+                nxt = s3_load<DIM, R>(src, min(k + kBlock, pend - 1));
+            } else {
+                in = s3_load<DIM, R>(src, k);
+            }
             Stencil<DIM, SHAPE, R> st;
             make_stencil<DIM, SHAPE, R, EDGE>(&V, in.x, st);
             const int l0[3] = {st.c[0] - c0[0], st.c[1] - c0[1], DIM == 3 ? st.c[2] - c0[2] : 0};
