@@ -79,12 +79,14 @@ __device__ __forceinline__ bool tile_interior(const View &V, const int c0[3]) {
 // cleared the step before).
 template <int DIM> constexpr bool kHalo = DIM == 2;
 
-// Consecutive tiles per XCD in the tile order of the sweeps (xcd_tile).  In
-// 2D, groups of four keep neighbouring tiles' shared cache lines in one L2
-// (cylinder: S2 −10 %, S3 −5 %).  3D keeps the round-robin order except in
-// S3: its S1 adds frame nodes atomically, and neighbouring tiles on one XCD
-// then contend (FP64 S1 +60 %).
-template <int DIM> constexpr int kXcdGroup = DIM == 2 ? 4 : 1;
+// Consecutive tiles per XCD in the tile order of the sweeps (xcd_tile).
+// Groups of four keep neighbouring tiles' shared cache lines in one L2
+// (cylinder: S2 −10 %, S3 −5 %; 256^3 blast in int64 fixed point: S1 −4 %,
+// S2 −1 %, where groups of two or eight gain less).  The other 3D
+// precision modes keep the round-robin order in S1 and S2, whose frame nodes
+// go through global atomics: FP64 atomics of neighbouring tiles on one XCD
+// contend (FP64 S1 +60 %).
+template <int DIM, int PREC> constexpr int kXcdGroup = DIM == 2 || PREC == P_F32_FIX ? 4 : 1;
 constexpr int kXcdGroupS3 = 4;
 
 // MASS0: value q = 0 is a mass (quantum q_m; the others are momenta, q_p).
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(WorkTab wt) {
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
     if (!P->active) return;
-    const int t = xcd_tile<kXcdGroup<DIM>>(blockIdx.x - wt.start[pi], P->ntiles);
+    const int t = xcd_tile<kXcdGroup<DIM, PREC>>(blockIdx.x - wt.start[pi], P->ntiles);
     // Field pointers of the staged particle arrays, read before any store
     // of the kernel so that they stay uniform (scalar) loads.
     const GLOBAL_AS R *src[NPF];
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p(WorkTab wt) {
     const int pi = find_prob(wt, blockIdx.x);
     const ProbDev *P = wt.prob[pi];
     if (!P->active) return;
-    const int t = xcd_tile<kXcdGroup<DIM>>(blockIdx.x - wt.start[pi], P->ntiles);
+    const int t = xcd_tile<kXcdGroup<DIM, PREC>>(blockIdx.x - wt.start[pi], P->ntiles);
     // Field pointers, read before any store of the kernel (uniform loads)
     const GLOBAL_AS R *src[NPF];
     const GLOBAL_AS uint32_t *idg;
@@ -1258,7 +1260,7 @@ __global__ __launch_bounds__(kBlock) void k_cellscan(WorkTab wt) {
     const int pi = find_prob(wt, blockIdx.x);
     ProbDev *P = wt.prob[pi];
     if (!P->active) return;
-    const int t = xcd_tile<kXcdGroup<DIM>>(blockIdx.x - wt.start[pi], P->ntiles);
+    const int t = xcd_tile<kXcdGroup<DIM, PREC>>(blockIdx.x - wt.start[pi], P->ntiles);
     uint32_t *out = P->offs[P->parity ^ 1];
     const uint32_t c = (uint32_t)t * kBlock + threadIdx.x;
     const bool fused = wt.max_tiles <= kFuseTiles;
@@ -1302,7 +1304,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_reduce(WorkTab wt) {
         const int pi = find_prob(wt, blockIdx.x);
         ProbDev *P = wt.prob[pi];
         if (!P->active) return;
-        const int t = xcd_tile<kXcdGroup<DIM>>(blockIdx.x - wt.start[pi], P->ntiles);
+        const int t = xcd_tile<kXcdGroup<DIM, PREC>>(blockIdx.x - wt.start[pi], P->ntiles);
         reduce_frame<SHAPE, PREC, 1 + 2 * DIM, true>(P, t, gmem((R *)P->gA[P->parity]), gmem((const A *)P->haloA));
     }
 }
