@@ -73,13 +73,6 @@ struct Layout {
     int has_obstacle;
 };
 
-int fields_used(int dim, int f) {
-    if (f >= PF_X && f < PF_X + 3) return f - PF_X < dim;
-    if (f >= PF_V && f < PF_V + 3) return f - PF_V < dim;
-    if (f >= PF_G && f < PF_G + 9) return f - PF_G < dim * dim;
-    return 1;
-}
-
 int check_desc(const mpm_desc *d, double *h_out) {
     if (!d) return MPM_E_ARG;
     if (d->dim != 2 && d->dim != 3) return MPM_E_ARG;
@@ -167,15 +160,14 @@ Layout make_layout(const mpm_desc *d) {
     L.acc_sz = d->precision == MPM_FP32_ACC_F32 ? 4 : 8;
     size_t o = 0;
     L.off_prob = o; o = align_up(o + sizeof(ProbDev));
-    // Fields of one parity follow each other at one stride (the update sweep
-    // addresses the G components as component 0 plus c strides).
+    // The stored fields of one parity are consecutive arrays one stride
+    // apart, field f at field_slot(dim, f) strides past the first: the update
+    // sweep addresses them that way.
+    const size_t fstride = align_up((size_t)L.np * L.real_sz);
     for (int p = 0; p < 2; ++p) {
-        for (int f = 0; f < PF_N; ++f) {
-            L.off_part[p][f] = (size_t)-1;
-            if (!fields_used(d->dim, f)) continue;
-            L.off_part[p][f] = o;
-            o = align_up(o + (size_t)L.np * L.real_sz);
-        }
+        for (int f = 0; f < PF_N; ++f)
+            L.off_part[p][f] = field_used(d->dim, f) ? o + (size_t)field_slot(d->dim, f) * fstride : (size_t)-1;
+        o += (size_t)field_slot(d->dim, PF_N) * fstride;
         L.off_pid[p] = o; o = align_up(o + (size_t)L.np * 4);
     }
     L.off_key = o; o = align_up(o + (size_t)L.np * 4);

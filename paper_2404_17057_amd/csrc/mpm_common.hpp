@@ -53,6 +53,20 @@ enum { PT_N = 8 };
 // is written by the last step of each run.
 enum { PF_X = 0, PF_V = 3, PF_M = 6, PF_RHO = 7, PF_E = 8, PF_G = 9, PF_D = 18, PF_N = 19 };
 
+// Whether a problem of dimension dim stores field f (X and V keep their
+// first dim components, G its first dim^2).
+__host__ __device__ constexpr bool field_used(int dim, int f) {
+    return f < PF_V ? f - PF_X < dim : f < PF_M ? f - PF_V < dim : (f >= PF_G && f < PF_D) ? f - PF_G < dim * dim : true;
+}
+// Position of field f among the stored fields of one parity (f = PF_N: how
+// many there are).  The workspace keeps the stored fields of a parity
+// consecutive, one stride apart, in this order.
+__host__ __device__ constexpr int field_slot(int dim, int f) {
+    int s = 0;
+    for (int g = 0; g < f; ++g) s += field_used(dim, g) ? 1 : 0;
+    return s;
+}
+
 // Tile sizes (cells) per dimension: one lane per cell, 256 lanes per group.
 template <int DIM> struct Tile;
 template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1, CELLS = 256; };

@@ -1420,37 +1420,55 @@ template <typename R> struct S3In {
     uint32_t id, rk;
 };
 
+// Particle fields of S3, source (this step's parity) and destination (the
+// next): stored field f of a parity lies field_slot(DIM, f) strides of fs
+// bytes past its first stored field f0.  Twenty-odd field pointers held
+// across the particle loop spill from the scalar registers and are reloaded
+// for every particle; a base and a stride are four registers, and the
+// addresses are formed at each load and store instead (empty asm below).
 template <int DIM, typename R> struct S3Src {
-    const GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d;
+    const GLOBAL_AS char *f0;
+    long long fs;
     const GLOBAL_AS uint32_t *id, *rank;
 };
 
-// Destination arrays of S3 (the next parity) and the next cell offsets.
 template <int DIM, typename R> struct S3Dst {
-    GLOBAL_AS R *x[3], *v[3], *M, *rho, *e, *d;
-    // G: component c (row-major) at g0 + c * gs (the components are
-    // consecutive particle fields of one size in the workspace)
-    GLOBAL_AS R *g0;
-    long long gs;
+    GLOBAL_AS char *f0;
+    long long fs;
     GLOBAL_AS uint32_t *id;
     const GLOBAL_AS uint32_t *noff;
     bool full_g;              // the last step of the run: write the whole G too
 };
 
+// Stored field F of a parity (first field f0, stride fs bytes).
+template <int DIM, int F, typename R, typename C>
+__device__ __forceinline__ auto field_ptr(C *f0, long long fs) {
+    using T = typename std::conditional<std::is_const<C>::value, const R, R>::type;
+    return (GLOBAL_AS T *)(f0 + field_slot(DIM, F) * fs);
+}
+
 template <int DIM, typename R>
 __device__ __forceinline__ S3In<R> s3_load(const S3Src<DIM, R> &sp, uint32_t k) {
+    // base and stride pass through an empty asm: the compiler cannot hoist
+    // the field addresses out of the loop (where they would spill)
+    const GLOBAL_AS char *f0 = sp.f0;
+    long long fs = sp.fs;
+    asm volatile("" : "+s"(f0), "+s"(fs));
     S3In<R> in;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { in.x[a] = 0; in.v[a] = 0; }
-    in.Dprev = ldk(sp.d, k);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        in.x[a] = ldk(sp.x[a], k);
-        in.v[a] = ldk(sp.v[a], k);
+    in.Dprev = ldk(field_ptr<DIM, PF_D, R>(f0, fs), k);
+    in.x[0] = ldk(field_ptr<DIM, PF_X + 0, R>(f0, fs), k);
+    in.x[1] = ldk(field_ptr<DIM, PF_X + 1, R>(f0, fs), k);
+    in.v[0] = ldk(field_ptr<DIM, PF_V + 0, R>(f0, fs), k);
+    in.v[1] = ldk(field_ptr<DIM, PF_V + 1, R>(f0, fs), k);
+    if constexpr (DIM == 3) {
+        in.x[2] = ldk(field_ptr<DIM, PF_X + 2, R>(f0, fs), k);
+        in.v[2] = ldk(field_ptr<DIM, PF_V + 2, R>(f0, fs), k);
     }
-    in.M = ldk(sp.M, k);
-    in.rho = ldk(sp.rho, k);
-    in.e = ldk(sp.e, k);
+    in.M = ldk(field_ptr<DIM, PF_M, R>(f0, fs), k);
+    in.rho = ldk(field_ptr<DIM, PF_RHO, R>(f0, fs), k);
+    in.e = ldk(field_ptr<DIM, PF_E, R>(f0, fs), k);
     in.id = ldk(sp.id, k);
     in.rk = ldk(sp.rank, k);
     return in;
@@ -1574,27 +1592,35 @@ __device__ __forceinline__ void s3_particle(const ProbDev *P, const View *V, con
         flags |= ERR_INTERNAL;
         return;
     }
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        stk(dst.x[a], slot, x[a]);
-        stk(dst.v[a], slot, v[a]);
+    GLOBAL_AS char *f0 = dst.f0;
+    long long fs = dst.fs;
+    asm volatile("" : "+s"(f0), "+s"(fs));
+    stk(field_ptr<DIM, PF_X + 0, R>(f0, fs), slot, x[0]);
+    stk(field_ptr<DIM, PF_X + 1, R>(f0, fs), slot, x[1]);
+    stk(field_ptr<DIM, PF_V + 0, R>(f0, fs), slot, v[0]);
+    stk(field_ptr<DIM, PF_V + 1, R>(f0, fs), slot, v[1]);
+    if constexpr (DIM == 3) {
+        stk(field_ptr<DIM, PF_X + 2, R>(f0, fs), slot, x[2]);
+        stk(field_ptr<DIM, PF_V + 2, R>(f0, fs), slot, v[2]);
     }
-    stk(dst.M, slot, M);
-    stk(dst.rho, slot, rhon);
-    stk(dst.e, slot, En);
+    stk(field_ptr<DIM, PF_M, R>(f0, fs), slot, M);
+    stk(field_ptr<DIM, PF_RHO, R>(f0, fs), slot, rhon);
+    stk(field_ptr<DIM, PF_E, R>(f0, fs), slot, En);
     // tr G of the stored gradient (zero for a recycled particle): the sum
     // the next step would form from the stored diagonal, the same bits
-    stk(dst.d, slot, mv == 1 ? (R)0 : D);
+    stk(field_ptr<DIM, PF_D, R>(f0, fs), slot, mv == 1 ? (R)0 : D);
     if (dst.full_g) {
-        // The empty asm makes base and stride new values here, so the nine
-        // component addresses are formed in this branch: hoisted out of the
-        // particle loop they were 18 more live scalar registers, which spilled
-        // and were reloaded for every particle.
-        GLOBAL_AS R *g0 = dst.g0;
-        long long gs = dst.gs;
-        asm volatile("" : "+s"(g0), "+s"(gs));
-#pragma unroll
-        for (int c = 0; c < DIM * DIM; ++c) stk(g0 + c * gs, slot, Gm[c]);
+        stk(field_ptr<DIM, PF_G + 0, R>(f0, fs), slot, Gm[0]);
+        stk(field_ptr<DIM, PF_G + 1, R>(f0, fs), slot, Gm[1]);
+        stk(field_ptr<DIM, PF_G + 2, R>(f0, fs), slot, Gm[2]);
+        stk(field_ptr<DIM, PF_G + 3, R>(f0, fs), slot, Gm[3]);
+        if constexpr (DIM == 3) {
+            stk(field_ptr<DIM, PF_G + 4, R>(f0, fs), slot, Gm[4]);
+            stk(field_ptr<DIM, PF_G + 5, R>(f0, fs), slot, Gm[5]);
+            stk(field_ptr<DIM, PF_G + 6, R>(f0, fs), slot, Gm[6]);
+            stk(field_ptr<DIM, PF_G + 7, R>(f0, fs), slot, Gm[7]);
+            stk(field_ptr<DIM, PF_G + 8, R>(f0, fs), slot, Gm[8]);
+        }
     }
     stk(dst.id, slot, id);
 
@@ -1634,36 +1660,17 @@ __global__ __launch_bounds__(kBlock, (kUpdateBlocks<DIM, PREC>)) void k_update(W
     const int t = xcd_tile<kXcdGroupS3>(blockIdx.x - wt.start[pi], P->ntiles);
     // Field pointers, read before any store of the kernel (uniform loads)
     S3Src<DIM, R> src;
-    {
-        const int par0 = P->parity;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int aa = a < DIM ? a : 0;
-            src.x[a] = gmem((const R *)P->part[par0][PF_X + aa]);
-            src.v[a] = gmem((const R *)P->part[par0][PF_V + aa]);
-        }
-        src.d = gmem((const R *)P->part[par0][PF_D]);
-        src.M = gmem((const R *)P->part[par0][PF_M]);
-        src.rho = gmem((const R *)P->part[par0][PF_RHO]);
-        src.e = gmem((const R *)P->part[par0][PF_E]);
-        src.id = gmem((const uint32_t *)P->pid[par0]);
-        src.rank = gmem((const uint32_t *)P->rank);
-    }
     S3Dst<DIM, R> dst;
     {
-        const int np1 = P->parity ^ 1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int aa = a < DIM ? a : 0;
-            dst.x[a] = gmem((R *)P->part[np1][PF_X + aa]);
-            dst.v[a] = gmem((R *)P->part[np1][PF_V + aa]);
-        }
-        dst.g0 = gmem((R *)P->part[np1][PF_G]);
-        dst.gs = ((const char *)P->part[np1][PF_G + 1] - (const char *)P->part[np1][PF_G]) / (long long)sizeof(R);
-        dst.M = gmem((R *)P->part[np1][PF_M]);
-        dst.rho = gmem((R *)P->part[np1][PF_RHO]);
-        dst.e = gmem((R *)P->part[np1][PF_E]);
-        dst.d = gmem((R *)P->part[np1][PF_D]);
+        const int par0 = P->parity, np1 = par0 ^ 1;
+        // stride between stored fields (X has at least two components)
+        const long long fs = (const char *)P->part[par0][PF_X + 1] - (const char *)P->part[par0][PF_X];
+        src.f0 = gmem((const char *)P->part[par0][PF_X]);
+        src.fs = fs;
+        src.id = gmem((const uint32_t *)P->pid[par0]);
+        src.rank = gmem((const uint32_t *)P->rank);
+        dst.f0 = gmem((char *)P->part[np1][PF_X]);
+        dst.fs = fs;
         // the run ends with this step when it is its last counted step or
         // reaches t_end (the same test the time-step kernel makes)
         const double t_end = P->t_end;
