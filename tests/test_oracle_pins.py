@@ -677,3 +677,39 @@ def test_fp32_state_option_rounds_storage_only():
     d = np.abs(ra - rb).max() / np.abs(ra).max()
     assert 0.0 < d <= 1e-5, d
     assert b.status()["t"] == pytest.approx(a.status()["t"], rel=1e-5)
+
+
+def test_blast_oracle_keeps_the_lattice_symmetries():
+    """An unjittered blast (a centred sphere of high pressure, walls on every
+    face, the clamped knots at both ends of each axis) is symmetric under the
+    mirror x -> 1 - x and under permutations of the axes, and the method
+    keeps every symmetry of its input.  After 3 oracle steps each particle's
+    density and energy equal its images', and its velocity is its image's
+    velocity mapped back, to FP64 rounding.  A slip that treats one axis
+    differently (a stencil weight or derivative taken from another axis, a
+    transposed G component, a wall condition on the wrong face) breaks it."""
+    n = 12
+    pb = W.blast3d(n=n, steps=3, jitter=0.0, radius=0.15, p_in=10.0, p_out=0.1)
+    h = pb.h
+    m = 2 * n
+    lat = np.rint(pb.x / (h / 2) - 0.5).astype(np.int64)        # lattice index per axis
+    assert np.abs(lat * (h / 2) + h / 4 - pb.x).max() < 1e-12
+    key = lat[0] + m * (lat[1] + m * lat[2])
+    inv = np.empty(key.size, np.int64)
+    inv[key] = np.arange(key.size)
+    # image particle of each particle, and how a velocity maps onto it
+    images = {
+        "mirror_x": (inv[(m - 1 - lat[0]) + m * (lat[1] + m * lat[2])], lambda v: np.stack([-v[0], v[1], v[2]])),
+        "swap_xy": (inv[lat[1] + m * (lat[0] + m * lat[2])], lambda v: np.stack([v[1], v[0], v[2]])),
+        "cycle_xyz": (inv[lat[2] + m * (lat[0] + m * lat[1])], lambda v: np.stack([v[2], v[0], v[1]])),
+    }
+    o = O.Oracle(pb)
+    assert o.step(3) == 0
+    rho, e, v = o.particles(O.F_RHO), o.particles(O.F_E), o.particles(O.F_V)
+    vscale = np.abs(v).max()
+    assert vscale > 0.1                       # the blast has started to move the gas
+    assert np.abs(rho - 1.0).max() > 1e-3     # and to compress it
+    for name, (img, vmap) in images.items():
+        assert np.abs(rho[img] - rho).max() <= 1e-12 * rho.max(), name
+        assert np.abs(e[img] - e).max() <= 1e-12 * e.max(), name
+        assert np.abs(v[:, img] - vmap(v)).max() <= 1e-12 * vscale, name
