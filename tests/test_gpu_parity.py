@@ -223,6 +223,46 @@ def test_batched_step_equals_single_problem_steps():
             assert np.array_equal(got[f], ref[f])
 
 
+def test_batched_3d_blasts_equal_single_problem_steps():
+    """Three 3D blasts of 16^3, 24^3 and 40^3 cells (16, 54 and 250 tiles:
+    fewer than one round of the grouped tile order, one round and a
+    remainder, several rounds and a remainder) stepped together, one batched
+    launch per sweep.  Fixed point (tiles grouped per XCD in S1 and S2):
+    every problem ends bit for bit where it ends alone, also when the batch
+    changes between calls.  FP64 (round-robin tile order, FP64 frame
+    atomics): after 2 batched steps every problem matches the oracle."""
+    _gpu()
+    pbs = [W.blast3d(n=16, steps=10, seed=1), W.blast3d(n=24, steps=10, seed=2),
+           W.blast3d(n=40, steps=10, seed=3)]
+    fs = [G.F_X, G.F_V, G.F_RHO, G.F_E]
+    alone = []
+    for pb in pbs:
+        s = G.Simulation(pb, G.FP32_FIX64)
+        s.step(10)
+        alone.append(s.read(fs))
+        s.close()
+    sims = [G.Simulation(pb, G.FP32_FIX64) for pb in pbs]
+    G.step_batch(sims, [10, 4, 10])
+    G.step_batch(sims[1:2], [6])
+    for s, ref in zip(sims, alone):
+        assert s.status()["step"] == 10
+        got = s.read(fs)
+        for f in fs:
+            assert np.array_equal(got[f], ref[f]), f
+        s.close()
+    sims = [G.Simulation(pb, G.FP64) for pb in pbs]
+    G.step_batch(sims, [2, 2, 2])
+    for pb, s in zip(pbs, sims):
+        o = O.Oracle(pb)
+        o.step(2)
+        got = s.read(fs)
+        for gf, of in [(G.F_X, O.F_X), (G.F_V, O.F_V), (G.F_RHO, O.F_RHO), (G.F_E, O.F_E)]:
+            e = rel_linf(got[gf], o.particles(of))
+            assert e <= 1e-9, (pb.name, gf, e)
+        assert s.status()["t"] == pytest.approx(o.status()["t"], rel=1e-14)
+        s.close()
+
+
 def test_blast3d_fp32_fix_against_oracle():
     _gpu()
     pb = W.blast3d(n=24, steps=20)
