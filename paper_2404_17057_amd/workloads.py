@@ -15,6 +15,9 @@ Workloads (all 2D unless stated, ideal gas gamma = 1.4):
                    field rho=1.4, p=1 so that c=1 and Mach = |u|.
 * ``blast3d``   -- 3D spherical blast in the unit cube: rho=1, p=1e-5, and an
                    inner sphere at p=1e3; walls everywhere.
+* ``sphere3d``  -- the cylinder's 3D counterpart: supersonic flow past a sphere
+                   in a channel, inflow at x_lo, outflow (recycling) at x_hi and
+                   optionally at the side faces, else walls.
 * ``quadrant``  -- 2x2-quadrant Riemann problem on the unit square, random
                    per-quadrant states; walls everywhere.
 * ``aerofoil``  -- transonic flow (Mach 0.73) past a NACA 4-digit section
@@ -328,6 +331,40 @@ def cylinder(nx=1024, ny=512, per_axis=2, mach=3.0, jitter=0.05, seed=DEFAULT_SE
         seed=seed, t_end=0.0, steps=steps, cell_mask=mask, node_normal=normal)
 
 
+def sphere3d(nx=64, per_axis=2, mach=3.0, jitter=0.05, seed=DEFAULT_SEED, shape=B2,
+             av_form=AV_PAPER, center=(0.3, 0.25, 0.25), radius=0.1, outflow_sides=False,
+             steps=100, cfl=0.3) -> Problem:
+    """The cylinder's 3D counterpart: Mach `mach` flow past a sphere in the
+    channel [0,1] x [0,0.5] x [0,0.5] (nx x nx/2 x nx/2 cells), the same gas
+    (rho = 1.4, p = 1, c = 1) and inflow at x_lo; outflow (recycling) at
+    x_hi, and at the four side faces too with `outflow_sides`, else walls
+    there.  It exercises the 3D inflow, outflow, recycling and obstacle
+    conditions that the all-wall blast does not reach."""
+    assert nx % 2 == 0
+    h = 1.0 / nx
+    n = (nx, nx // 2, nx // 2)
+    lo = (0.0, 0.0, 0.0)
+    hi = (1.0, n[1] * h, n[2] * h)
+    rho0, p0, gamma = 1.4, 1.0, 1.4
+    mask, normal = circle_obstacle(n, lo, h, 3, shape, center, radius)
+    rng = np.random.default_rng(seed)
+    x, _ = _lattice(n, lo, h, 3, per_axis, jitter, rng, cell_ok=1 - mask)
+    N = x.shape[1]
+    ppc = per_axis ** 3
+    m0 = rho0 * h ** 3 / ppc
+    v = np.zeros((3, N))
+    v[0] = mach
+    side = (OUTFLOW, OUTFLOW) if outflow_sides else (WALL, WALL)
+    return Problem(
+        name=f"sphere3d_{nx}_ppc{ppc}", dim=3, n=n, lo=lo, hi=hi,
+        faces=((INFLOW, OUTFLOW), side, side),
+        x=x, v=v, mass=np.full(N, m0), rho=np.full(N, rho0),
+        eint=np.full(N, p0 / ((gamma - 1.0) * rho0)), ids=np.arange(N, dtype=np.uint32),
+        shape=shape, av_form=av_form, gamma=gamma, cfl=cfl,
+        inflow_rho=rho0, inflow_p=p0, inflow_u=(mach, 0.0, 0.0), recycle_mass=m0,
+        seed=seed, t_end=0.0, steps=steps, cell_mask=mask, node_normal=normal)
+
+
 def aerofoil(nx=640, per_axis=2, mach=0.73, code="2412", alpha_deg=-3.5, chord=0.12,
              leading_edge=(0.1, 0.135), jitter=0.05, seed=DEFAULT_SEED, shape=B2,
              av_form=AV_PAPER, steps=2000, cfl=0.3, n_side=200) -> Problem:
@@ -505,6 +542,7 @@ WORKLOADS = {
     "sod": sod,
     "cylinder": cylinder,
     "blast3d": blast3d,
+    "sphere3d": sphere3d,
     "quadrant": quadrant,
 }
 
