@@ -370,6 +370,42 @@ def test_sphere3d_run_against_oracle(prec, tol, open_sides):
     s.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _3d_mode_case(name):
+    pb = {"blast3d_24": lambda: W.blast3d(n=24, steps=10),
+          "sphere3d_24_open": lambda: W.sphere3d(nx=24, steps=10, outflow_sides=True)}[name]()
+    o = O.Oracle(pb)
+    assert o.step(10) == 0
+    out = {f: o.particles(f) for f in (O.F_RHO, O.F_E, O.F_V)}
+    o.close()
+    return pb, out
+
+
+@pytest.mark.parametrize("name", ["blast3d_24", "sphere3d_24_open"])
+@pytest.mark.parametrize("prec", [G.FP32_ACC_F64, G.FP32_ACC_F32])
+def test_3d_fp32_state_modes_against_oracle(prec, name):
+    """The two other FP32-state precisions in 3D (the frame nodes and the
+    LDS tile summed with FP64 or with FP32 atomics), 10 steps of the blast
+    and of the open sphere channel against the oracle.  Bar: the FP32 state's
+    few tens of roundings per particle-step over 10 steps, 10 x 30 x 6e-8 =
+    1.8e-5, plus FP32 accumulation for the FP32-atomic mode (a node sums
+    a few hundred contributions, each rounded to 6e-8 of the running sum):
+    1e-4 relative L1."""
+    _gpu()
+    pb, ref = _3d_mode_case(name)
+    s = G.Simulation(pb, prec)
+    s.step(10)
+    st = s.status()
+    assert st["rc"] == 0 and st["step"] == 10
+    errs = {k: rel_l1(s.field(gf), ref[of]) for k, gf, of in
+            (("rho", G.F_RHO, O.F_RHO), ("e", G.F_E, O.F_E), ("V", G.F_V, O.F_V))}
+    print(name, prec, "rel L1", errs, flush=True)
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, e)
+    assert s.counters()[1] == 0
+    s.close()
+
+
 def test_mass_and_ids_preserved_with_recycling():
     _gpu()
     pb = W.cylinder(nx=64, ny=32, steps=200)
