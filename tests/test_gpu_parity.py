@@ -139,6 +139,34 @@ def test_fp64_gradient_after_several_steps_matches_oracle():
     assert rel_linf(got[G.F_RHO], o.particles(O.F_RHO)) <= 1e-9
 
 
+@pytest.mark.parametrize("prec,tol", [(G.FP64, 1e-9), (G.FP32_FIX64, 1e-4)])
+def test_textbook_av_form_run_against_oracle(prec, tol):
+    """The textbook form of the artificial viscosity (MPM_AV_BOOK) on the
+    cylinder, 8 steps: Q enters from the second step (it takes the stored
+    tr G of the step before) and, with the bow shock forming, changes the
+    density by 7 % and the energy by 16 % against the paper's form (oracle,
+    checked here), so a GPU path that took the wrong form would fail.  FP64
+    is compared by relative L-inf (per-particle, rounding only), the FP32
+    state by relative L1."""
+    _gpu()
+    pb = W.cylinder(nx=128, ny=64, steps=8, av_form=W.AV_BOOK)
+    o = O.Oracle(pb)
+    o.step(8)
+    other = O.Oracle(W.cylinder(nx=128, ny=64, steps=8, av_form=W.AV_PAPER))
+    other.step(8)
+    rho_o, e_o, q_o = o.particles(O.F_RHO), o.particles(O.F_E), o.particles(O.F_Q)
+    assert rel_linf(other.particles(O.F_RHO), rho_o) > 1e-2
+    s = G.Simulation(pb, prec)
+    s.step(8)
+    assert s.status()["rc"] == 0
+    got = s.read([G.F_RHO, G.F_E, G.F_Q])
+    norm = rel_linf if prec == G.FP64 else rel_l1
+    assert norm(got[G.F_RHO], rho_o) <= tol
+    assert norm(got[G.F_E], e_o) <= tol
+    assert norm(got[G.F_Q], q_o) <= (tol if prec == G.FP64 else 1e-3)
+    s.close()
+
+
 def test_3d_fix64_blast_matches_oracle_and_is_order_free():
     """The 3D fixed-point path, whose S1 and S2 keep the first z-slab pass's
     per-particle results in LDS for the other two (the tile's first 2048
