@@ -612,6 +612,28 @@ def test_q1_fp64_one_step_matches_oracle(name):
         assert e <= 1e-9, (name, gf, e)
 
 
+@pytest.mark.parametrize("prec,tol", [(G.FP64, 1e-9), (G.FP32_FIX64, 1e-4)])
+def test_q1_3d_runs_against_oracle(prec, tol):
+    """The trilinear basis in 3D over 8 steps: the blast 24^3 (walls) and the
+    open sphere channel (inflow, recycling, obstacle), FP64 by relative
+    L-inf per particle and the fixed-point path (two z-slab passes of 2x2
+    nodes) by relative L1."""
+    _gpu()
+    for pb in (W.blast3d(n=24, steps=8, shape=W.Q1),
+               W.sphere3d(nx=24, steps=8, shape=W.Q1, outflow_sides=True)):
+        o = O.Oracle(pb)
+        o.step(8)
+        s = G.Simulation(pb, prec)
+        s.step(8)
+        assert s.status()["rc"] == 0
+        norm = rel_linf if prec == G.FP64 else rel_l1
+        for gf, of in [(G.F_X, O.F_X), (G.F_V, O.F_V), (G.F_RHO, O.F_RHO), (G.F_E, O.F_E)]:
+            e = norm(s.field(gf), o.particles(of))
+            assert e <= tol, (pb.name, gf, e)
+        s.close()
+        o.close()
+
+
 def test_q1_sod_bounded_run_fp64_and_fix():
     """Q1 Sod over a bounded horizon.  With the bilinear basis the particle
     noise from cell crossings makes the run chaotic: in the oracle, a 1e-13
