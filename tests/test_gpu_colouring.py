@@ -3,7 +3,7 @@ are done by grid colouring (Sec. 5) -- 3^dim passes, one thread per cell of
 a colour, plain adds, the particles of a cell in increasing id -- against
 the FP64 oracle and for bitwise reproducibility without fixed point.
 
-* one step, six workloads (2D and 3D, with obstacles, a ragged grid): every
+* one step, seven workloads (2D and 3D, with obstacles, inflow and outflow, a ragged grid): every
   grid snapshot and the particle state to 1e-9 relative L-inf;
 * a full Sod run to t = 0.2: relative L1 of density <= 1e-6;
 * two runs of 30 steps of the cylinder, and a run from a permuted input:
@@ -41,6 +41,7 @@ CASES = {
     "blast3d_24": lambda: W.blast3d(n=24, steps=5),
     "cylinder36x18_ragged": lambda: W.cylinder(nx=36, ny=18, steps=5, radius=0.08, center=(0.3, 0.25)),
     "aerofoil160x108": lambda: W.aerofoil(nx=160, steps=10),
+    "sphere3d_24_open": lambda: W.sphere3d(nx=24, steps=5, outflow_sides=True),
 }
 
 
