@@ -353,6 +353,30 @@ def test_recycled_particle_position_follows_the_hash():
     assert o.particles(O.F_M)[j] == pb.mass[j]
 
 
+def test_recycled_particle_position_follows_the_hash_3d():
+    """In 3D a recycled particle draws each transverse coordinate from its
+    own stream of the hash: y from splitmix64(seed ^ step<<32 ^ id) and z
+    from the same word with 1<<56 set (axis a uses (a-1)<<56).  The two
+    fractions must differ, so a recycler that drew both from one stream (or
+    swapped them) fails."""
+    pb = W.sphere3d(nx=16, steps=1)
+    k = int(np.argmax(pb.x[0]))            # right-most particle (its id is k)
+    assert pb.ids[k] == k
+    pb.x[0, k] = 1.0 - 1e-6
+    o = O.Oracle(pb)
+    o.step(1)
+    x = o.particles(O.F_X)
+    u = []
+    for a in (1, 2):
+        word = (pb.seed ^ (0 << 32) ^ k ^ ((a - 1) << 56)) & 0xFFFFFFFFFFFFFFFF
+        u.append((O.splitmix64(word) >> 11) * 2.0 ** -53)
+        assert x[a, k] == pytest.approx(pb.lo[a] + (pb.hi[a] - pb.lo[a]) * u[-1], rel=0, abs=1e-15), a
+    assert abs(u[0] - u[1]) > 1e-3
+    assert 0 <= x[0, k] < 4 * o.status()["dt_last"]
+    assert np.array_equal(o.particles(O.F_V)[:, k], [3.0, 0.0, 0.0])
+    assert o.particles(O.F_M)[k] == pb.recycle_mass
+
+
 def test_projected_density_read_out():
     """The grid-projected density sum M phi / sum (M / rho) phi is the
     density itself wherever the gas has one density (whatever the masses and
