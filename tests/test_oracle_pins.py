@@ -315,6 +315,46 @@ def test_total_mass_constant_with_recycling():
     assert o.status()["wall_escapes"] == 0
 
 
+def test_boundary_conditions_in_a_step_3d():
+    """The same post-conditions in 3D (the sphere channel): walls on the y and
+    z faces null the normal momentum and force of their boundary nodes,
+    inflow nodes carry m u_in and no force, and obstacle nodes (those whose
+    lower-corner cell lies in the sphere) keep no inward momentum or force,
+    while the raw maps had some."""
+    pb = W.sphere3d(nx=24, steps=3)
+    o = O.Oracle(pb)
+    o.step(3)
+    nx, ny, nz = pb.node_counts()
+    shp = (nz, ny, nx)
+    m = o.grid(O.G_M).reshape(shp)
+    pu = o.grid(O.G_PUPD).reshape((3,) + shp)
+    p = o.grid(O.G_P).reshape((3,) + shp)
+    f = o.grid(O.G_F).reshape((3,) + shp)
+    fbc = o.grid(O.G_FBC).reshape((3,) + shp)
+    p2 = o.grid(O.G_P2).reshape((3,) + shp)
+    # y walls (axis 1 of the arrays) and z walls (axis 0)
+    for g in (pu, p2, fbc):
+        assert np.abs(g[1][:, 0, :]).max() == 0 and np.abs(g[1][:, -1, :]).max() == 0
+        assert np.abs(g[2][0, :, :]).max() == 0 and np.abs(g[2][-1, :, :]).max() == 0
+    # inflow face x = 0 (its edges are walls too): momentum = m u_in, no force
+    inner = (slice(1, -1), slice(1, -1), 0)
+    assert np.allclose(pu[0][inner], 3.0 * m[inner], rtol=1e-14)
+    assert np.abs(pu[1][inner]).max() == 0 and np.abs(pu[2][inner]).max() == 0
+    assert np.abs(fbc[:, :, :, 0]).max() == 0
+    # obstacle nodes
+    nrm = pb.node_normal.reshape((3,) + shp)
+    mask = pb.cell_mask.reshape(pb.n[2], pb.n[1], pb.n[0])
+    jz, jy, jx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    obst = mask[np.clip(jz - 1, 0, pb.n[2] - 1), np.clip(jy - 1, 0, pb.n[1] - 1),
+                np.clip(jx - 1, 0, pb.n[0] - 1)] != 0
+    assert obst.sum() > 0
+    assert ((p2 * nrm).sum(axis=0)[obst] >= -1e-15).all()
+    assert ((p * nrm).sum(axis=0)[obst] < 0).any()
+    fscale = np.abs(f).max()
+    assert ((f * nrm).sum(axis=0)[obst] < -1e-6 * fscale).sum() > 10
+    assert ((fbc * nrm).sum(axis=0)[obst] >= -1e-15 * fscale).all()
+
+
 def test_recycled_particle_position_follows_the_hash():
     """A particle about to leave through the outflow re-enters at
     x - L with y drawn from splitmix64(seed ^ step<<32 ^ id), and takes the
