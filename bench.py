@@ -295,6 +295,12 @@ def blast3d(args):
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                 "sweeps_frac": {k: round(sb[k] / (sw[k] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
                                 for k in sb if sw.get(k)}}
+        # measured HBM bytes and VALU issue of the dominant sweep from the
+        # committed counters (None once the kernels changed)
+        counters = measured_counters(dom, pb.name, kernel_source_hash())
+        valu = counters.get("sq_insts_valu")
+        roof["traffic"] = counters.get("bytes_per_launch")
+        roof["valu_issue_frac"] = round(valu * 4 / (1024 * 2.4e9 * dom_ms * 1e-3), 3) if valu else None
     out = {"workload": f"blast3d_{args.blast_n}^3_ppc8", "particles": pb.n_particles,
            "steps": args.blast_steps, "warmup": r["warmup_steps"],
            "value": round(r["value"], 1), "unit": "particle-steps/s",
