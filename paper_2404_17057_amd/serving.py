@@ -169,12 +169,21 @@ def summarize(done: Sequence[Completed]) -> Dict[str, float]:
     tts = np.array([d.time_to_solution for d in done])
     work = float(sum(d.particles * d.steps for d in done))
     span = max(d.finished for d in done) - min(d.arrival for d in done)
+    rate = work / span
+    # the requests behind the tail: their size, queueing and the time their
+    # own work would take at the stream's aggregate rate
+    slowest = sorted(done, key=lambda d: d.time_to_solution, reverse=True)[:3]
     return {
         "requests": len(done),
         "p50_time_to_solution_s": float(np.percentile(tts, 50)),
         "p99_time_to_solution_s": float(np.percentile(tts, 99)),
         "mean_queue_s": float(np.mean([d.admitted - d.arrival for d in done])),
-        "aggregate_particle_steps_per_s": work / span,
+        "aggregate_particle_steps_per_s": rate,
         "makespan_s": span,
         "errors": int(sum(1 for d in done if d.status != 0)),
+        "slowest": [{"req_id": d.req_id, "particle_steps": d.particles * d.steps,
+                     "queue_s": round(d.admitted - d.arrival, 4),
+                     "time_to_solution_s": round(d.time_to_solution, 4),
+                     "own_work_at_aggregate_rate_s": round(d.particles * d.steps / rate, 4)}
+                    for d in slowest],
     }
