@@ -145,9 +145,13 @@ template <typename R> __device__ __forceinline__ R recip(R x) {
 template <typename R> __device__ __forceinline__ R eos_p(R gamma, R rho, R e) {
     return (gamma - (R)1) * rho * e;                 // perfect gas (Sec. 2.1)
 }
+// Sound speed sqrt(max(gamma P / rho, 0)): in FP32 the hardware square
+// root (within 1 ulp; it feeds only the artificial viscosity, whose FP32
+// inputs carry that much already), in FP64 the correctly rounded one.
 template <typename R> __device__ __forceinline__ R sound(R gamma, R rho, R p) {
     const R c2 = gamma * p * recip(rho);
-    return c2 > (R)0 ? sqrt(c2) : (R)0;
+    if constexpr (sizeof(R) == 4) return c2 > (R)0 ? __builtin_amdgcn_sqrtf(c2) : (R)0;
+    else return c2 > (R)0 ? sqrt(c2) : (R)0;
 }
 // Artificial pressure (Sec. 2.1, eq. muart), only for div v < 0.
 template <typename R>
