@@ -757,21 +757,24 @@ def test_blast3d_full_size_symmetry():
     assert np.abs(cons[1:4]).max() <= 1e-9 * math.sqrt(2 * cons[0] * cons[5])   # measured 1.3e-11
 
 
-def test_fix64_checkpoint_resume_is_bitwise():
+@pytest.mark.parametrize("name", ["cylinder_128x64", "sphere3d_32_open"])
+def test_fix64_checkpoint_resume_is_bitwise(name):
     """A run interrupted after 15 of 40 steps, read back (every particle
     field, G and id included, with t, dt_next and the step count) and
     re-initialised from what was read, ends bit-identical to the
-    uninterrupted run: the cylinder, whose outflow recycling is keyed by the
-    step count."""
+    uninterrupted run: the cylinder and the open 3D sphere channel, whose
+    outflow recycling is keyed by the step count."""
     _gpu()
     import dataclasses
-    pb = W.cylinder(nx=128, ny=64, steps=40)
+    pb = {"cylinder_128x64": lambda: W.cylinder(nx=128, ny=64, steps=40),
+          "sphere3d_32_open": lambda: W.sphere3d(nx=32, steps=40, outflow_sides=True)}[name]()
     pb = dataclasses.replace(pb, rho_ref=1.4, u_ref=16.0)
     fields = [G.F_X, G.F_V, G.F_M, G.F_RHO, G.F_E, G.F_G, G.F_ID]
     full = G.Simulation(pb, G.FP32_FIX64)
     full.step(40)
     ref = full.read(fields)
     ref_st = full.status()
+    assert full.counters()[2] > 0          # particles were recycled
     full.close()
     first = G.Simulation(pb, G.FP32_FIX64)
     first.step(15)
