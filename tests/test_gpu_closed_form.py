@@ -104,14 +104,17 @@ def test_wall_escape_is_clamped_and_counted(prec):
     assert s.status()["rc"] == 0
 
 
-def test_fixed_point_overflow_is_reported():
+@pytest.mark.parametrize("name", ["sod_64x2", "blast3d_16"])
+def test_fixed_point_overflow_is_reported(name):
     """Quanta far below the mass of a cell (a reference density 1e-9 of the
     real one) put the node sums beyond the int64 range the kernels accept:
-    the step raises the sticky overflow error and the handle stops."""
+    the step raises the sticky overflow error and the handle stops (2D: the
+    halo-record flush; 3D: the frame atomics)."""
     _gpu()
-    pb = W.sod(nx=64, ny=2, t_end=0.0)
+    pb = {"sod_64x2": lambda: W.sod(nx=64, ny=2, t_end=0.0),
+          "blast3d_16": lambda: W.blast3d(n=16, steps=2)}[name]()
     pb.rho_ref = 1e-9
-    print("fixed-point overflow: sod 64x2, rho_ref 1e-9", flush=True)
+    print(f"fixed-point overflow: {name}, rho_ref 1e-9", flush=True)
     s = G.Simulation(pb, G.FP32_FIX64)
     s.step(2)
     st = s.status()
