@@ -743,7 +743,8 @@ def test_fp32_state_option_rounds_storage_only():
     assert b.status()["t"] == pytest.approx(a.status()["t"], rel=1e-5)
 
 
-def test_blast_oracle_keeps_the_lattice_symmetries():
+@pytest.mark.parametrize("shape", [W.B2, W.Q1])
+def test_blast_oracle_keeps_the_lattice_symmetries(shape):
     """An unjittered blast (a centred sphere of high pressure, walls on every
     face, the clamped knots at both ends of each axis) is symmetric under the
     mirror x -> 1 - x and under permutations of the axes, and the method
@@ -753,7 +754,7 @@ def test_blast_oracle_keeps_the_lattice_symmetries():
     differently (a stencil weight or derivative taken from another axis, a
     transposed G component, a wall condition on the wrong face) breaks it."""
     n = 12
-    pb = W.blast3d(n=n, steps=3, jitter=0.0, radius=0.15, p_in=10.0, p_out=0.1)
+    pb = W.blast3d(n=n, steps=3, jitter=0.0, radius=0.15, p_in=10.0, p_out=0.1, shape=shape)
     h = pb.h
     m = 2 * n
     lat = np.rint(pb.x / (h / 2) - 0.5).astype(np.int64)        # lattice index per axis
